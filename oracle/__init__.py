@@ -1,0 +1,301 @@
+"""FP64 CPU oracle of the known-operator CT path (PYRO-NN, arXiv 1904.13342).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check in
+``__graft_entry__.py`` and the CPU-baseline leg of ``bench.py`` may import
+this package.  It shares no code with the HIP library; both take their
+inputs from ``synth``.
+
+The arithmetic lives in ``oracle.c`` (plain C99, double precision, OpenMP over
+output elements, no fast-math).  This module builds it with gcc, loads it with
+ctypes and composes the FBP / FDK pipeline of Eq. 4 / Eq. 5:
+``x = B( filter( W_red * W_cos * p ) )``.
+
+Array conventions (float64, C-contiguous):
+  2D image ``[ny, nx]``, sinogram ``[n_proj, nu]``;
+  3D volume ``[nz, ny, nx]``, projections ``[n_proj, nv, nu]``.
+
+Parity unpinned: none (see the oracle test-suite for the pin of every entry).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force=True):
+    """Compile oracle.c with gcc (-O2 -fopenmp, IEEE semantics)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-D_GNU_SOURCE", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("sx", ctypes.c_double), ("sy", ctypes.c_double), ("sz", ctypes.c_double),
+        ("ox", ctypes.c_double), ("oy", ctypes.c_double), ("oz", ctypes.c_double),
+        ("nu", ctypes.c_int), ("nv", ctypes.c_int),
+        ("du", ctypes.c_double), ("dv", ctypes.c_double),
+        ("n_proj", ctypes.c_int),
+        ("range", ctypes.c_double),
+        ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
+        ("step", ctypes.c_double),
+    ]
+
+
+_KIND = {"par2d": 0, "fan2d": 1, "cone3d": 2}
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        dp, ip, gp = P(ctypes.c_double), P(ctypes.c_int), P(_Geom)
+        sig = {
+            "ora_project": (None, [gp, dp, dp, ip, ctypes.c_int]),
+            "ora_project_adjoint": (None, [gp, dp, dp]),
+            "ora_count_samples": (ctypes.c_longlong, [gp, ip, ctypes.c_int]),
+            "ora_backproject": (None, [gp, dp, dp, ip, ctypes.c_int]),
+            "ora_backproject_adjoint": (None, [gp, dp, dp]),
+            "ora_ramlak_filter": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]),
+            "ora_circular_filter": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]),
+            "ora_ramlak_response": (None, [ctypes.c_int, ctypes.c_double, dp]),
+            "ora_ramp_response": (None, [ctypes.c_int, ctypes.c_double, dp]),
+            "ora_cosine_weights": (None, [gp, dp]),
+            "ora_parker": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "ora_redundancy_weights": (None, [gp, dp]),
+            "ora_projection_matrices": (None, [gp, dp]),
+            "ora_num_threads": (ctypes.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def geom(spec):
+    """Oracle geometry record from a ``synth.GeometrySpec``."""
+    g = _Geom()
+    g.kind = _KIND[spec.kind]
+    org = spec.origin
+    if spec.ndim == 2:
+        (g.ny, g.nx), (g.sy, g.sx), (g.oy, g.ox) = spec.vol_shape, spec.vol_spacing, org
+        g.nz, g.sz, g.oz = 1, 1.0, 0.0
+        g.nu, g.nv, g.du, g.dv = spec.det_shape[0], 1, spec.det_spacing[0], 1.0
+    else:
+        (g.nz, g.ny, g.nx), (g.sz, g.sy, g.sx), (g.oz, g.oy, g.ox) = spec.vol_shape, spec.vol_spacing, org
+        (g.nv, g.nu), (g.dv, g.du) = spec.det_shape, spec.det_spacing
+    g.n_proj = spec.n_proj
+    g.range = spec.angular_range
+    g.sid, g.sdd = spec.sid, spec.sdd
+    g.step = spec.step
+    return g
+
+
+def num_threads():
+    return _load().ora_num_threads()
+
+
+def _vol3(spec, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return f.reshape((1,) + tuple(spec.vol_shape)) if spec.ndim == 2 else f.reshape(spec.vol_shape)
+
+
+def _proj_shape(spec):
+    return (spec.n_proj, 1, spec.det_shape[0]) if spec.ndim == 2 else (spec.n_proj,) + tuple(spec.det_shape)
+
+
+def _out_proj(spec, p):
+    return p.reshape(spec.n_proj, spec.det_shape[0]) if spec.ndim == 2 else p
+
+
+def _out_vol(spec, f):
+    return f.reshape(spec.vol_shape)
+
+
+def _idx(sel):
+    return None if sel is None else np.ascontiguousarray(sel, dtype=np.int32)
+
+
+# ------------------------------------------------------------------ operators
+
+def project(spec, f, views=None):
+    """Ray-driven forward projection A f (fixed-step multilinear sampling).
+    With ``views`` only those views are computed; the others are zero."""
+    g = geom(spec)
+    f3 = _vol3(spec, f)
+    p = np.zeros(_proj_shape(spec))
+    v = _idx(views)
+    _load().ora_project(ctypes.byref(g), _dp(f3), _dp(p), _ip(v), 0 if v is None else len(v))
+    return _out_proj(spec, p)
+
+
+def project_adjoint(spec, p):
+    """Exact transpose A^T of ``project`` (scatter)."""
+    g = geom(spec)
+    p3 = np.ascontiguousarray(p, dtype=np.float64).reshape(_proj_shape(spec))
+    f = np.zeros((g.nz, g.ny, g.nx))
+    _load().ora_project_adjoint(ctypes.byref(g), _dp(p3), _dp(f))
+    return _out_vol(spec, f)
+
+
+def count_samples(spec, views=None):
+    g = geom(spec)
+    v = _idx(views)
+    return int(_load().ora_count_samples(ctypes.byref(g), _ip(v), 0 if v is None else len(v)))
+
+
+def backproject(spec, q, slices=None):
+    """Voxel-driven, distance-weighted back-projection B q.  With ``slices``
+    only those z slices are computed; the others are zero."""
+    g = geom(spec)
+    q3 = np.ascontiguousarray(q, dtype=np.float64).reshape(_proj_shape(spec))
+    f = np.zeros((g.nz, g.ny, g.nx))
+    s = _idx(slices)
+    _load().ora_backproject(ctypes.byref(g), _dp(q3), _dp(f), _ip(s), 0 if s is None else len(s))
+    return _out_vol(spec, f)
+
+
+def backproject_adjoint(spec, f):
+    """Exact transpose B^T of ``backproject`` (scatter)."""
+    g = geom(spec)
+    f3 = _vol3(spec, f)
+    q = np.zeros(_proj_shape(spec))
+    _load().ora_backproject_adjoint(ctypes.byref(g), _dp(f3), _dp(q))
+    return _out_proj(spec, q)
+
+
+# -------------------------------------------------------------------- filters
+
+def tau(spec):
+    """Iso-scaled detector sample spacing of the ramp filter."""
+    du = spec.det_spacing[-1]
+    return du if spec.kind == "par2d" else du * spec.sid / spec.sdd
+
+
+def fft_size(nu):
+    """Smallest power of two >= 2*nu - 1 (linear convolution without wrap)."""
+    m = 1
+    while m < 2 * nu - 1:
+        m *= 2
+    return m
+
+
+def ramlak_filter(rows, t):
+    rows = np.ascontiguousarray(rows, dtype=np.float64)
+    nu = rows.shape[-1]
+    out = np.empty_like(rows)
+    _load().ora_ramlak_filter(rows.size // nu, nu, float(t), _dp(rows), _dp(out))
+    return out
+
+
+def circular_filter(rows, K):
+    rows = np.ascontiguousarray(rows, dtype=np.float64)
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    nu = rows.shape[-1]
+    out = np.empty_like(rows)
+    _load().ora_circular_filter(rows.size // nu, nu, len(K), _dp(K), _dp(rows), _dp(out))
+    return out
+
+
+def ramlak_response(M, t):
+    K = np.empty(M)
+    _load().ora_ramlak_response(M, float(t), _dp(K))
+    return K
+
+
+def ramp_response(M, t):
+    K = np.empty(M)
+    _load().ora_ramp_response(M, float(t), _dp(K))
+    return K
+
+
+# -------------------------------------------------------------------- weights
+
+def cosine_weights(spec):
+    g = geom(spec)
+    w = np.empty((g.nv, g.nu))
+    _load().ora_cosine_weights(ctypes.byref(g), _dp(w))
+    return w
+
+
+def redundancy_weights(spec):
+    g = geom(spec)
+    w = np.empty((g.n_proj, g.nu))
+    _load().ora_redundancy_weights(ctypes.byref(g), _dp(w))
+    return w
+
+
+def parker(beta, gamma, delta):
+    return float(_load().ora_parker(float(beta), float(gamma), float(delta)))
+
+
+def projection_matrices(spec):
+    g = geom(spec)
+    P = np.empty((g.n_proj, 3, 4))
+    _load().ora_projection_matrices(ctypes.byref(g), _dp(P))
+    return P
+
+
+# ------------------------------------------------------------------ pipelines
+
+def weight(spec, p, W_red=None, W=None):
+    """W_red * W_cos (* W) * p  (Eq. 5 without the filter)."""
+    p3 = np.asarray(p, dtype=np.float64).reshape(_proj_shape(spec))
+    wc = cosine_weights(spec)
+    wr = redundancy_weights(spec) if W_red is None else np.asarray(W_red, dtype=np.float64)
+    out = p3 * wc[None, :, :] * wr[:, None, :]
+    if W is not None:
+        out = out * np.asarray(W, dtype=np.float64).reshape(wc.shape)[None]
+    return out
+
+
+def filter_projections(spec, p, K=None):
+    """Row-wise ramp filtering: Ram-Lak as a direct linear convolution when
+    ``K`` is None, otherwise the circular filter with response ``K``."""
+    p3 = np.asarray(p, dtype=np.float64).reshape(_proj_shape(spec))
+    if K is None:
+        return ramlak_filter(p3, tau(spec))
+    return circular_filter(p3, K)
+
+
+def fbp(spec, p, W_red=None, K=None, W=None, slices=None):
+    """FBP / FDK, Eq. 4 / Eq. 5: x = B filter(W_red W_cos p)."""
+    q = filter_projections(spec, weight(spec, p, W_red=W_red, W=W), K=K)
+    return backproject(spec, q, slices=slices)
+
+
+__all__ = [
+    "build", "geom", "num_threads", "project", "project_adjoint", "count_samples", "backproject",
+    "backproject_adjoint", "tau", "fft_size", "ramlak_filter", "circular_filter", "ramlak_response",
+    "ramp_response", "cosine_weights", "redundancy_weights", "parker", "projection_matrices", "weight",
+    "filter_projections", "fbp",
+]
