@@ -1,0 +1,179 @@
+/*
+ * pyrohip.h -- C ABI of the MI355X-native known-operator CT library
+ * (ray-driven forward projection, voxel-driven back-projection, ramp-filtered
+ * FBP / FDK) following PYRO-NN, arXiv 1904.13342.
+ *
+ * All entry points are plain C: geometry records, host or device pointers,
+ * sizes and a HIP stream handle passed as void*.  No entry point throws,
+ * exits or prints; every one returns a ph_status.
+ *
+ * Geometry (Sec. II.C.1 lists the attributes: volume shape and spacing,
+ * detector shape and spacing, number of projections, angular range, SID and
+ * SDD; Sec. II.C.3 adds the trajectory as central ray vectors in 2D and
+ * projection matrices in 3D).  Conventions:
+ *   - voxel (ix,iy,iz) centre at world (ox+ix*sx, oy+iy*sy, oz+iz*sz) mm,
+ *     arrays are C-contiguous with x fastest: 2D image [batch][ny][nx],
+ *     3D volume [batch][nz][ny][nx];
+ *   - detector pixel (i,j): row i (v, along +z), column j (u); pixel centre
+ *     u_j = (j-(nu-1)/2)*du, v_i = (i-(nv-1)/2)*dv; arrays [batch][n_proj][nu]
+ *     in 2D and [batch][n_proj][nv][nu] in 3D, u fastest;
+ *   - 2D view k has central ray vector c_k = ray_vecs[k] (unit, world x,y);
+ *     detector axis e_u = (-c_y, c_x); parallel rays pass through u*e_u with
+ *     direction c_k; fan rays leave the source -SID*c_k for the flat detector
+ *     centred at (SDD-SID)*c_k;
+ *   - 3D view k has projection matrix mats[k] (row-major 3x4) mapping
+ *     homogeneous world mm to (j*w, i*w, w); the library rescales each matrix
+ *     so that w is the depth in mm along the central ray (positive in front
+ *     of the source).
+ *
+ * Memory: every array argument named img/vol/sino/proj/K/W_red/W/ws is a
+ * DEVICE pointer owned by the caller; ray_vecs and mats are HOST pointers,
+ * read during the call.  Outputs are overwritten, never accumulated.  Work is
+ * enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ * asynchronous.  The library keeps a small per-device cache of derived
+ * per-view parameters (uploaded once per distinct geometry with a blocking
+ * copy); besides that it allocates no device memory: FBP/FDK scratch comes
+ * from the caller's workspace `ws` sized by ph_workspace_bytes_*.
+ *
+ * Storage type (ph_dtype) applies to img/vol/sino/proj; arithmetic is FP32
+ * and geometry is always FP32.  FP16 and BF16 are rounded to nearest-even on
+ * store.
+ */
+#ifndef PYROHIP_H
+#define PYROHIP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PH_OK = 0,
+    PH_ERR_NULL = -1,        /* a required pointer is NULL */
+    PH_ERR_SHAPE = -2,       /* non-positive size, batch < 1, bad filter length */
+    PH_ERR_GEOMETRY = -3,    /* non-positive or non-finite spacing/step, SDD <= SID,
+                                source inside the volume, singular or non-finite matrix */
+    PH_ERR_DTYPE = -4,       /* unknown storage type */
+    PH_ERR_WORKSPACE = -5,   /* workspace NULL or smaller than required */
+    PH_ERR_HIP = -6,         /* a HIP call or kernel launch failed */
+    PH_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+} ph_status;
+
+typedef enum { PH_F32 = 0, PH_F16 = 1, PH_BF16 = 2 } ph_dtype;
+
+typedef struct {
+    int vol_shape[2];       /* (ny, nx) */
+    float vol_spacing[2];   /* (sy, sx) mm */
+    float vol_origin[2];    /* (oy, ox): world mm of the centre of pixel (0,0) */
+    int det_shape;          /* nu */
+    float det_spacing;      /* du mm */
+    int n_proj;
+    float angular_range;    /* rad; view k nominally at k*range/n_proj */
+    float sid, sdd;         /* mm; ignored by the parallel-beam calls */
+    float step_mm;          /* ray sampling step of the forward projector; <= 0 -> half the smallest spacing */
+} ph_geom2d;
+
+typedef struct {
+    int vol_shape[3];       /* (nz, ny, nx) */
+    float vol_spacing[3];   /* (sz, sy, sx) mm */
+    float vol_origin[3];    /* (oz, oy, ox): world mm of the centre of voxel (0,0,0) */
+    int det_shape[2];       /* (nv, nu) */
+    float det_spacing[2];   /* (dv, du) mm */
+    int n_proj;
+    float angular_range;    /* rad */
+    float sid, sdd;         /* mm */
+    float step_mm;          /* <= 0 -> half the smallest spacing */
+} ph_geom3d;
+
+/* Human-readable name of a status code (static string). */
+const char *ph_status_string(int status);
+
+/* Library version and the GPU architecture it was built for. */
+const char *ph_version(void);
+
+/* ------------------------------------------------------------------ trajectories
+ * Sec. II.C.3: basic helpers that compute the trajectory of a circular scan
+ * from the geometry.  Host only, no GPU needed.  View k at angle
+ * beta_k = k*range/n_proj, counter-clockwise about +z. */
+
+/* ray_vecs: host float[n_proj][2] <- (cos beta_k, sin beta_k). */
+int ph_ray_vectors_2d(const ph_geom2d *g, float *ray_vecs);
+
+/* mats: host float[n_proj][3][4] <- Kint [R | -R S] with R rows (e_u; e_v; c),
+ * S = -SID*c, Kint = [[SDD/du, 0, (nu-1)/2], [0, SDD/dv, (nv-1)/2], [0,0,1]]. */
+int ph_projection_matrices_3d(const ph_geom3d *g, float *mats);
+
+/* --------------------------------------------------- forward projection A
+ * Sec. II.B.2 (ray-driven forward projection, one ray per detector pixel,
+ * absorption accumulated along it; Eq. 1 A x = p).  Every ray r is sampled on
+ * the lattice a_r + k*step*d_r, k in Z, with a_r the point of the ray closest
+ * to the isocentre and d_r its unit direction; the volume is interpolated
+ * bi-/trilinearly with zero outside the grid; p_r = step * sum_k.
+ *   img  : device [batch][ny][nx]        (dtype)      input
+ *   sino : device [batch][n_proj][nu]    (dtype)      output
+ *   vol  : device [batch][nz][ny][nx]    (dtype)      input
+ *   proj : device [batch][n_proj][nv][nu](dtype)      output */
+int ph_project_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
+                     int dtype, void *stream);
+int ph_project_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
+                     int dtype, void *stream);
+int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
+                      int dtype, void *stream);
+
+/* ------------------------------------------------- back-projection B
+ * Sec. II.B.2 (voxel-driven back-projection: every voxel accumulates the
+ * interpolated value at its projection in every view).  Detector values are
+ * interpolated linearly (2D) / bilinearly (3D) with zero outside the
+ * detector; the sum is multiplied by dbeta = range/n_proj and, for fan and
+ * cone beams, each term by the distance weight (SID/w)^2, w the depth of the
+ * voxel along the central ray.  Same arrays as the forward calls with the
+ * roles of input and output exchanged. */
+int ph_backproject_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
+                         int dtype, void *stream);
+int ph_backproject_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
+                         int dtype, void *stream);
+int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
+                          int dtype, void *stream);
+
+/* --------------------------------------------- weighting + ramp filtering
+ * Eq. 4 / Eq. 5 without the back-projection: q = F^H K F (W_red * W_cos * W * p),
+ * row by row (detector rows along u).  Sec. II.C.4 (Ramp / Ram-Lak filters as
+ * a diagonal multiply in the Fourier domain), Sec. II.C.5 (cosine and
+ * redundancy weights).
+ *   K     : device float[M] real response on the M-point DFT grid, or NULL for
+ *           Ram-Lak with sample spacing tau (du for parallel, du*SID/SDD for
+ *           fan/cone) and M = smallest power of two >= 2*nu-1 (then the row
+ *           filter is an exact linear convolution);  M must be a power of two
+ *           in [max(16, nu), 8192];  with K given the output is
+ *           Re IDFT_M(K . DFT_M(zero-padded row)), first nu samples;
+ *   W_red : device float[n_proj][nu] or NULL -> parallel: pi/range;
+ *           fan/cone: 1/2 for a full turn, Parker for a short scan;
+ *   W     : device float[nv][nu] extra per-pixel weight or NULL (3D only);
+ *   out   : device float[batch][n_proj](nv)[nu], FP32 regardless of dtype.
+ * M = 0 with K = NULL selects the default length. */
+int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
+                        const float *W_red, int batch, int dtype, void *stream);
+int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M,
+                        const float *W_red, const float *W, int batch, int dtype, void *stream);
+
+/* ------------------------------------------------------- FBP / FDK
+ * Eq. 4 (FBP) and Eq. 5 (FDK network): x = B F^H K F W_red W_cos p.
+ * Workspace: ws of ws_bytes >= ph_workspace_bytes_*() device bytes holds the
+ * filtered projections. */
+size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch);
+size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch);
+
+int ph_fbp_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, const float *K, int M,
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream);
+int ph_fbp_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, const float *K, int M,
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream);
+int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
+                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, int dtype,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYROHIP_H */

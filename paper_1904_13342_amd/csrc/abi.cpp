@@ -1,0 +1,850 @@
+// C-ABI entry points of libpyrohip: argument validation (on the host, before
+// any HIP call), derivation of per-view kernel parameters in FP64, a small
+// per-device cache of those parameters, and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pyrohip.h"
+#include "common.h"
+
+using namespace ph;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// ------------------------------------------------------------------ caching
+// Derived per-view tables are uploaded once per (device, content) and kept
+// until the process ends (or evicted past kMaxEntries).  The key is the exact
+// bytes of everything the table depends on.
+
+struct Entry {
+    int device;
+    std::string key;
+    void *ptr;
+};
+std::mutex g_mu;
+std::vector<Entry> g_cache;
+constexpr size_t kMaxEntries = 64;
+
+template <typename Build>
+const void *cached(const std::string &key, Build build, int *status)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *status = PH_ERR_HIP;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (size_t n = 0; n < g_cache.size(); ++n) {
+        if (g_cache[n].device == dev && g_cache[n].key == key) {
+            Entry e = g_cache[n];
+            g_cache.erase(g_cache.begin() + (long)n);
+            g_cache.push_back(e);
+            return e.ptr;
+        }
+    }
+    std::vector<unsigned char> host = build();
+    void *p = nullptr;
+    if (hipMalloc(&p, host.size()) != hipSuccess) {
+        *status = PH_ERR_HIP;
+        return nullptr;
+    }
+    if (hipMemcpy(p, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);
+        *status = PH_ERR_HIP;
+        return nullptr;
+    }
+    if (g_cache.size() >= kMaxEntries) {
+        // hipFree waits for outstanding work that may still read the entry
+        (void)hipFree(g_cache.front().ptr);
+        g_cache.erase(g_cache.begin());
+    }
+    g_cache.push_back(Entry{dev, key, p});
+    return p;
+}
+
+template <typename T>
+std::vector<unsigned char> as_bytes(const std::vector<T> &v)
+{
+    std::vector<unsigned char> out(v.size() * sizeof(T));
+    std::memcpy(out.data(), v.data(), out.size());
+    return out;
+}
+
+template <typename T>
+void append(std::string &key, const T *p, size_t n)
+{
+    key.append(reinterpret_cast<const char *>(p), n * sizeof(T));
+}
+
+// ------------------------------------------------------------- validation
+
+int check_dtype(int dtype) { return (dtype == PH_F32 || dtype == PH_F16 || dtype == PH_BF16) ? PH_OK : PH_ERR_DTYPE; }
+
+double default_step(double step, double smin) { return step > 0.0 ? step : 0.5 * smin; }
+
+int make_geom2d(const ph_geom2d *g, bool fan, Geom2D *o)
+{
+    if (!g)
+        return PH_ERR_NULL;
+    if (g->vol_shape[0] < 1 || g->vol_shape[1] < 1 || g->det_shape < 1 || g->n_proj < 1)
+        return PH_ERR_SHAPE;
+    if (!finite_pos(g->vol_spacing[0]) || !finite_pos(g->vol_spacing[1]) || !finite_pos(g->det_spacing) ||
+        !finite_pos(g->angular_range) || !std::isfinite(g->vol_origin[0]) || !std::isfinite(g->vol_origin[1]) ||
+        !std::isfinite(g->step_mm))
+        return PH_ERR_GEOMETRY;
+    if (fan && !(finite_pos(g->sid) && std::isfinite(g->sdd) && g->sdd > g->sid))
+        return PH_ERR_GEOMETRY;
+    o->ny = g->vol_shape[0];
+    o->nx = g->vol_shape[1];
+    o->sy = g->vol_spacing[0];
+    o->sx = g->vol_spacing[1];
+    o->oy = g->vol_origin[0];
+    o->ox = g->vol_origin[1];
+    o->inv_sx = (float)(1.0 / g->vol_spacing[1]);
+    o->inv_sy = (float)(1.0 / g->vol_spacing[0]);
+    o->nu = g->det_shape;
+    o->du = g->det_spacing;
+    o->cu = 0.5f * (float)(g->det_shape - 1);
+    o->n_proj = g->n_proj;
+    o->sid = fan ? g->sid : 0.0f;
+    o->sdd = fan ? g->sdd : 0.0f;
+    o->step = (float)default_step(g->step_mm, std::fmin(g->vol_spacing[0], g->vol_spacing[1]));
+    o->dbeta = (float)((double)g->angular_range / g->n_proj);
+    return PH_OK;
+}
+
+int make_geom3d(const ph_geom3d *g, Geom3D *o)
+{
+    if (!g)
+        return PH_ERR_NULL;
+    for (int a = 0; a < 3; ++a)
+        if (g->vol_shape[a] < 1)
+            return PH_ERR_SHAPE;
+    if (g->det_shape[0] < 1 || g->det_shape[1] < 1 || g->n_proj < 1)
+        return PH_ERR_SHAPE;
+    for (int a = 0; a < 3; ++a)
+        if (!finite_pos(g->vol_spacing[a]) || !std::isfinite(g->vol_origin[a]))
+            return PH_ERR_GEOMETRY;
+    if (!finite_pos(g->det_spacing[0]) || !finite_pos(g->det_spacing[1]) || !finite_pos(g->angular_range) ||
+        !std::isfinite(g->step_mm) || !finite_pos(g->sid) || !std::isfinite(g->sdd) || !(g->sdd > g->sid))
+        return PH_ERR_GEOMETRY;
+    o->nz = g->vol_shape[0];
+    o->ny = g->vol_shape[1];
+    o->nx = g->vol_shape[2];
+    o->oz = g->vol_origin[0];
+    o->oy = g->vol_origin[1];
+    o->ox = g->vol_origin[2];
+    o->inv_sz = (float)(1.0 / g->vol_spacing[0]);
+    o->inv_sy = (float)(1.0 / g->vol_spacing[1]);
+    o->inv_sx = (float)(1.0 / g->vol_spacing[2]);
+    o->nv = g->det_shape[0];
+    o->nu = g->det_shape[1];
+    o->dv = g->det_spacing[0];
+    o->du = g->det_spacing[1];
+    o->cv = 0.5f * (float)(g->det_shape[0] - 1);
+    o->cu = 0.5f * (float)(g->det_shape[1] - 1);
+    o->n_proj = g->n_proj;
+    o->sid = g->sid;
+    o->sdd = g->sdd;
+    o->step = (float)default_step(
+        g->step_mm, std::fmin(g->vol_spacing[0], std::fmin(g->vol_spacing[1], g->vol_spacing[2])));
+    o->dbeta = (float)((double)g->angular_range / g->n_proj);
+    return PH_OK;
+}
+
+// Unit central-ray vectors of a 2D trajectory; for fan beams every view must
+// see the whole image support (index box [-1, N]) in front of the source.
+int views2d(const ph_geom2d *g, bool fan, const float *rv, std::vector<float2> *out)
+{
+    out->resize((size_t)g->n_proj);
+    const double y0 = g->vol_origin[0] - g->vol_spacing[0], y1 = g->vol_origin[0] + g->vol_shape[0] * (double)g->vol_spacing[0];
+    const double x0 = g->vol_origin[1] - g->vol_spacing[1], x1 = g->vol_origin[1] + g->vol_shape[1] * (double)g->vol_spacing[1];
+    for (int k = 0; k < g->n_proj; ++k) {
+        const double cx = rv[2 * k], cy = rv[2 * k + 1];
+        const double n = std::sqrt(cx * cx + cy * cy);
+        if (!std::isfinite(n) || n <= 0.0)
+            return PH_ERR_GEOMETRY;
+        (*out)[(size_t)k] = make_float2((float)(cx / n), (float)(cy / n));
+        if (fan) {
+            for (int c = 0; c < 4; ++c) {
+                const double x = (c & 1) ? x1 : x0, y = (c & 2) ? y1 : y0;
+                if (!(g->sid + (x * cx + y * cy) / n > 0.0))
+                    return PH_ERR_GEOMETRY;
+            }
+        }
+    }
+    return PH_OK;
+}
+
+// Normalised projection matrices (w = depth in mm, positive in front of the
+// source), checked to be finite and non-singular, with the whole volume
+// support (index box [-1, N] per axis) in front of every source.
+int normalised_mats(const ph_geom3d *g, const float *mats, std::vector<double> *P)
+{
+    P->assign((size_t)g->n_proj * 12, 0.0);
+    double lo[3], hi[3], ctr[3];
+    for (int a = 0; a < 3; ++a) {  // world x, y, z
+        const int ai = 2 - a;
+        lo[a] = g->vol_origin[ai] - g->vol_spacing[ai];
+        hi[a] = g->vol_origin[ai] + g->vol_shape[ai] * (double)g->vol_spacing[ai];
+        ctr[a] = g->vol_origin[ai] + 0.5 * (g->vol_shape[ai] - 1) * (double)g->vol_spacing[ai];
+    }
+    for (int k = 0; k < g->n_proj; ++k) {
+        double m[12];
+        for (int t = 0; t < 12; ++t) {
+            m[t] = mats[12 * k + t];
+            if (!std::isfinite(m[t]))
+                return PH_ERR_GEOMETRY;
+        }
+        const double det = m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
+                           m[2] * (m[4] * m[9] - m[5] * m[8]);
+        const double n0 = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        const double n1 = std::sqrt(m[4] * m[4] + m[5] * m[5] + m[6] * m[6]);
+        const double n2 = std::sqrt(m[8] * m[8] + m[9] * m[9] + m[10] * m[10]);
+        if (!(n2 > 0.0) || !(std::fabs(det) > 1e-9 * n0 * n1 * n2))
+            return PH_ERR_GEOMETRY;
+        double s = 1.0 / n2;
+        if (m[8] * ctr[0] + m[9] * ctr[1] + m[10] * ctr[2] + m[11] < 0.0)
+            s = -s;
+        for (int t = 0; t < 12; ++t)
+            (*P)[12 * (size_t)k + t] = s * m[t];
+        const double *r2 = &(*P)[12 * (size_t)k + 8];
+        for (int c = 0; c < 8; ++c) {
+            const double x = (c & 1) ? hi[0] : lo[0], y = (c & 2) ? hi[1] : lo[1], z = (c & 4) ? hi[2] : lo[2];
+            if (!(r2[0] * x + r2[1] * y + r2[2] * z + r2[3] > 0.0))
+                return PH_ERR_GEOMETRY;
+        }
+    }
+    return PH_OK;
+}
+
+// Back-projector rows over centred voxel indices, and whether the trajectory
+// is a rotation about z (no z term in the u and w rows).
+void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeBPView> *out, bool *axial)
+{
+    const double cu = 0.5 * (g->det_shape[1] - 1), cv = 0.5 * (g->det_shape[0] - 1);
+    const double s[3] = {g->vol_spacing[2], g->vol_spacing[1], g->vol_spacing[0]};
+    double oc[3];
+    for (int a = 0; a < 3; ++a)
+        oc[a] = g->vol_origin[2 - a] + 0.5 * (g->vol_shape[2 - a] - 1) * (double)g->vol_spacing[2 - a];
+    out->resize((size_t)g->n_proj);
+    *axial = true;
+    for (int k = 0; k < g->n_proj; ++k) {
+        const double *m = &P[12 * (size_t)k];
+        double r[3][4];
+        for (int t = 0; t < 4; ++t) {
+            r[0][t] = m[t] - cu * m[8 + t];
+            r[1][t] = m[4 + t] - cv * m[8 + t];
+            r[2][t] = m[8 + t];
+        }
+        ConeBPView &v = (*out)[(size_t)k];
+        for (int row = 0; row < 3; ++row) {
+            for (int a = 0; a < 3; ++a)
+                v.r[row][a] = (float)(r[row][a] * s[a]);
+            v.r[row][3] = (float)(r[row][0] * oc[0] + r[row][1] * oc[1] + r[row][2] * oc[2] + r[row][3]);
+        }
+        if (v.r[0][2] != 0.0f || v.r[2][2] != 0.0f)
+            *axial = false;
+    }
+}
+
+// Forward-projector rays: source S = -M^-1 p4 and the direction
+// M^-1 (j, i, 1) written around the detector centre.
+void fp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeFPView> *out)
+{
+    const double cu = 0.5 * (g->det_shape[1] - 1), cv = 0.5 * (g->det_shape[0] - 1);
+    out->resize((size_t)g->n_proj);
+    for (int k = 0; k < g->n_proj; ++k) {
+        const double *m = &P[12 * (size_t)k];
+        const double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], gg = m[8], h = m[9], i = m[10];
+        const double det = a * (e * i - f * h) - b * (d * i - f * gg) + c * (d * h - e * gg);
+        const double inv[3][3] = {{(e * i - f * h) / det, (c * h - b * i) / det, (b * f - c * e) / det},
+                                  {(f * gg - d * i) / det, (a * i - c * gg) / det, (c * d - a * f) / det},
+                                  {(d * h - e * gg) / det, (b * gg - a * h) / det, (a * e - b * d) / det}};
+        double S[3], d0[3], du[3], dv[3];
+        for (int r = 0; r < 3; ++r) {
+            S[r] = -(inv[r][0] * m[3] + inv[r][1] * m[7] + inv[r][2] * m[11]);
+            du[r] = inv[r][0];
+            dv[r] = inv[r][1];
+            d0[r] = cu * inv[r][0] + cv * inv[r][1] + inv[r][2];
+        }
+        ConeFPView &v = (*out)[(size_t)k];
+        for (int r = 0; r < 3; ++r) {
+            v.s[r] = (float)S[r];
+            v.d0[r] = (float)d0[r];
+            v.du[r] = (float)du[r];
+            v.dv[r] = (float)dv[r];
+        }
+    }
+}
+
+// --------------------------------------------------------- filter tables
+
+bool is_pow2(int m) { return m > 0 && (m & (m - 1)) == 0; }
+
+int default_fft_size(int nu)
+{
+    int m = 16;
+    while (m < 2 * nu - 1)
+        m *= 2;
+    return m;
+}
+
+int ilog2(int m)
+{
+    int l = 0;
+    while ((1 << l) < m)
+        ++l;
+    return l;
+}
+
+double ramlak_tap(long n, double tau)
+{
+    if (n == 0)
+        return 1.0 / (4.0 * tau * tau);
+    if (n % 2 == 0)
+        return 0.0;
+    return -1.0 / ((double)n * (double)n * kPi * kPi * tau * tau);
+}
+
+const float *ramlak_table(int M, double tau, int *st)
+{
+    std::string key = "ramlak";
+    append(key, &M, 1);
+    append(key, &tau, 1);
+    return (const float *)cached(
+        key,
+        [&] {
+            std::vector<float> K((size_t)M);
+            for (int k = 0; k < M; ++k) {
+                double acc = ramlak_tap(0, tau);
+                for (int n = 1; n < M; n += 2) {  // odd taps only; even taps are zero
+                    const long nn = n <= M / 2 ? n : n - M;
+                    acc += ramlak_tap(nn, tau) * std::cos(2.0 * kPi * (double)(((long)k * n) % M) / M);
+                }
+                K[(size_t)k] = (float)(tau * acc);
+            }
+            return as_bytes(K);
+        },
+        st);
+}
+
+const float2 *twiddle_table(int M, int *st)
+{
+    std::string key = "twiddle";
+    append(key, &M, 1);
+    return (const float2 *)cached(
+        key,
+        [&] {
+            std::vector<float2> t((size_t)M / 2);
+            for (int n = 0; n < M / 2; ++n)
+                t[(size_t)n] = make_float2((float)std::cos(2.0 * kPi * n / M), (float)-std::sin(2.0 * kPi * n / M));
+            return as_bytes(t);
+        },
+        st);
+}
+
+// Default redundancy weights: parallel pi/range; fan/cone 1/2 for a full
+// turn, Parker (delta = (range - pi)/2) for a short scan.
+double parker(double beta, double gamma, double delta)
+{
+    const double a = delta - gamma, b = delta + gamma;
+    if (a > 0.0 && beta < 2.0 * a) {
+        const double s = std::sin(0.25 * kPi * beta / a);
+        return s * s;
+    }
+    if (beta < kPi - 2.0 * gamma)
+        return 1.0;
+    if (b > 0.0 && beta <= kPi + 2.0 * delta) {
+        const double s = std::sin(0.25 * kPi * (kPi + 2.0 * delta - beta) / b);
+        return s * s;
+    }
+    return 0.0;
+}
+
+const float *wred_table(int kind, int n_proj, int nu, double du, double range, double sdd, int *st)
+{
+    std::string key = "wred";
+    append(key, &kind, 1);
+    append(key, &n_proj, 1);
+    append(key, &nu, 1);
+    append(key, &du, 1);
+    append(key, &range, 1);
+    append(key, &sdd, 1);
+    return (const float *)cached(
+        key,
+        [&] {
+            std::vector<float> w((size_t)n_proj * nu);
+            const bool full = std::fabs(range - 2.0 * kPi) <= 1e-6 * 2.0 * kPi;
+            const double delta = 0.5 * (range - kPi);
+            for (int k = 0; k < n_proj; ++k) {
+                const double beta = range * k / n_proj;
+                for (int j = 0; j < nu; ++j) {
+                    double v;
+                    if (kind == 0)
+                        v = kPi / range;
+                    else if (full)
+                        v = 0.5;
+                    else
+                        v = parker(beta, std::atan((j - 0.5 * (nu - 1)) * du / sdd), delta);
+                    w[(size_t)k * nu + j] = (float)v;
+                }
+            }
+            return as_bytes(w);
+        },
+        st);
+}
+
+// --------------------------------------------------------- shared drivers
+
+int to_status(hipError_t e) { return e == hipSuccess ? PH_OK : PH_ERR_HIP; }
+
+int prep2d(const ph_geom2d *g, bool fan, const float *rv, Geom2D *G, const float2 **views)
+{
+    int st = make_geom2d(g, fan, G);
+    if (st != PH_OK)
+        return st;
+    if (!rv)
+        return PH_ERR_NULL;
+    std::vector<float2> v;
+    st = views2d(g, fan, rv, &v);
+    if (st != PH_OK)
+        return st;
+    std::string key = fan ? "v2f" : "v2p";
+    append(key, g, 1);
+    append(key, rv, 2 * (size_t)g->n_proj);
+    st = PH_OK;
+    *views = (const float2 *)cached(key, [&] { return as_bytes(v); }, &st);
+    return st;
+}
+
+// Host-only validation of a 3D call's geometry and matrices.
+int validate3d(const ph_geom3d *g, const float *mats, Geom3D *G, std::vector<double> *P)
+{
+    int st = make_geom3d(g, G);
+    if (st != PH_OK)
+        return st;
+    if (!mats)
+        return PH_ERR_NULL;
+    return normalised_mats(g, mats, P);
+}
+
+// Per-view tables of a validated 3D call (uploaded on first use).
+int upload3d(const ph_geom3d *g, const float *mats, const std::vector<double> &P, bool for_bp, const void **views,
+             bool *axial)
+{
+    std::string key = for_bp ? "bp3" : "fp3";
+    append(key, g, 1);
+    append(key, mats, 12 * (size_t)g->n_proj);
+    int st = PH_OK;
+    if (for_bp) {
+        std::vector<ConeBPView> v;
+        bp_views(g, P, &v, axial);
+        *views = cached(key, [&] { return as_bytes(v); }, &st);
+    } else {
+        std::vector<ConeFPView> v;
+        fp_views(g, P, &v);
+        *views = cached(key, [&] { return as_bytes(v); }, &st);
+    }
+    return st;
+}
+
+int prep3d(const ph_geom3d *g, const float *mats, bool for_bp, Geom3D *G, const void **views, bool *axial)
+{
+    std::vector<double> P;
+    int st = validate3d(g, mats, G, &P);
+    if (st != PH_OK)
+        return st;
+    return upload3d(g, mats, P, for_bp, views, axial);
+}
+
+// Host-only check of the filter length; returns the length to use in *Mout.
+int filter_len(const float *K, int M, int nu, int *Mout)
+{
+    if (K) {
+        if (!is_pow2(M) || M < 16 || M < nu || M > 4096)
+            return PH_ERR_SHAPE;
+    } else {
+        if (M == 0)
+            M = default_fft_size(nu);
+        if (!is_pow2(M) || M < 2 * nu - 1 || M > 4096)
+            return PH_ERR_SHAPE;
+    }
+    *Mout = M;
+    return PH_OK;
+}
+
+// Filter arguments of a validated call (M from filter_len); uploads the
+// default tables on first use.
+int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, double dv, double sid, double sdd,
+                double range, const float *K, int M, const float *W_red, const float *W, FilterArgs *a)
+{
+    int st = PH_OK;
+    const double tau = kind == 0 ? du : du * sid / sdd;
+    a->nu = nu;
+    a->nv = nv;
+    a->n_proj = n_proj;
+    a->batch = batch;
+    a->M = M;
+    a->log2M = ilog2(M);
+    a->du = (float)du;
+    a->dv = (float)dv;
+    a->cu = 0.5f * (float)(nu - 1);
+    a->cv = 0.5f * (float)(nv - 1);
+    a->cos_sdd = kind == 0 ? 0.0f : (float)sdd;
+    a->K = K ? K : ramlak_table(M, tau, &st);
+    if (st != PH_OK)
+        return st;
+    a->tw = twiddle_table(M, &st);
+    if (st != PH_OK)
+        return st;
+    a->W_red = W_red ? W_red : wred_table(kind, n_proj, nu, du, range, sdd, &st);
+    if (st != PH_OK)
+        return st;
+    a->W = W;
+    return PH_OK;
+}
+
+size_t round_up(size_t n) { return (n + 255) & ~(size_t)255; }
+
+int project2d(const ph_geom2d *g, bool fan, const float *rv, const void *img, void *sino, int batch, int dtype,
+              void *stream)
+{
+    if (!img || !sino)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom2D G;
+    const float2 *views = nullptr;
+    st = prep2d(g, fan, rv, &G, &views);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_project_2d(dtype, fan, G, views, img, sino, batch, (hipStream_t)stream));
+}
+
+int backproject2d(const ph_geom2d *g, bool fan, const float *rv, const void *sino, void *img, int batch, int dtype,
+                  void *stream)
+{
+    if (!img || !sino)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom2D G;
+    const float2 *views = nullptr;
+    st = prep2d(g, fan, rv, &G, &views);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_backproject_2d(dtype, fan, G, views, sino, false, img, batch, (hipStream_t)stream));
+}
+
+int weight_filter2d(const ph_geom2d *g, bool fan, const void *sino, float *out, const float *K, int M,
+                    const float *W_red, int batch, int dtype, void *stream)
+{
+    if (!sino || !out)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom2D G;
+    st = make_geom2d(g, fan, &G);
+    if (st != PH_OK)
+        return st;
+    st = filter_len(K, M, g->det_shape, &M);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+                     g->angular_range, K, M, W_red, nullptr, &a);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_weight_filter(dtype, a, sino, out, (hipStream_t)stream));
+}
+
+int fbp2d(const ph_geom2d *g, bool fan, const float *rv, const void *sino, void *img, const float *K, int M,
+          const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    if (!sino || !img)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom2D G;
+    st = make_geom2d(g, fan, &G);
+    if (st != PH_OK)
+        return st;
+    if (!rv)
+        return PH_ERR_NULL;
+    {
+        std::vector<float2> tmp;
+        st = views2d(g, fan, rv, &tmp);
+        if (st != PH_OK)
+            return st;
+    }
+    if (!ws || ws_bytes < ph_workspace_bytes_2d(g, batch))
+        return PH_ERR_WORKSPACE;
+    st = filter_len(K, M, g->det_shape, &M);
+    if (st != PH_OK)
+        return st;
+    const float2 *views = nullptr;
+    st = prep2d(g, fan, rv, &G, &views);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+                     g->angular_range, K, M, W_red, nullptr, &a);
+    if (st != PH_OK)
+        return st;
+    float *q = (float *)ws;
+    st = to_status(launch_weight_filter(dtype, a, sino, q, (hipStream_t)stream));
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_backproject_2d(dtype, fan, G, views, q, true, img, batch, (hipStream_t)stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ph_status_string(int s)
+{
+    switch (s) {
+    case PH_OK: return "ok";
+    case PH_ERR_NULL: return "null pointer argument";
+    case PH_ERR_SHAPE: return "invalid shape, batch or filter length";
+    case PH_ERR_GEOMETRY: return "invalid geometry";
+    case PH_ERR_DTYPE: return "unknown storage dtype";
+    case PH_ERR_WORKSPACE: return "workspace missing or too small";
+    case PH_ERR_HIP: return "HIP runtime error";
+    case PH_ERR_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char *ph_version(void) { return "pyrohip 0.1 (gfx950)"; }
+
+int ph_ray_vectors_2d(const ph_geom2d *g, float *ray_vecs)
+{
+    if (!g || !ray_vecs)
+        return PH_ERR_NULL;
+    if (g->n_proj < 1)
+        return PH_ERR_SHAPE;
+    if (!finite_pos(g->angular_range))
+        return PH_ERR_GEOMETRY;
+    for (int k = 0; k < g->n_proj; ++k) {
+        const double b = (double)g->angular_range * k / g->n_proj;
+        ray_vecs[2 * k] = (float)std::cos(b);
+        ray_vecs[2 * k + 1] = (float)std::sin(b);
+    }
+    return PH_OK;
+}
+
+int ph_projection_matrices_3d(const ph_geom3d *g, float *mats)
+{
+    if (!g || !mats)
+        return PH_ERR_NULL;
+    if (g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1)
+        return PH_ERR_SHAPE;
+    if (!finite_pos(g->angular_range) || !finite_pos(g->det_spacing[0]) || !finite_pos(g->det_spacing[1]) ||
+        !finite_pos(g->sid) || !std::isfinite(g->sdd) || !(g->sdd > g->sid))
+        return PH_ERR_GEOMETRY;
+    const double cu = 0.5 * (g->det_shape[1] - 1), cv = 0.5 * (g->det_shape[0] - 1);
+    const double fu = g->sdd / (double)g->det_spacing[1], fv = g->sdd / (double)g->det_spacing[0];
+    for (int k = 0; k < g->n_proj; ++k) {
+        const double b = (double)g->angular_range * k / g->n_proj;
+        const double c[3] = {std::cos(b), std::sin(b), 0.0}, eu[3] = {-std::sin(b), std::cos(b), 0.0};
+        const double ev[3] = {0.0, 0.0, 1.0};
+        // R rows (e_u; e_v; c); translation -R S with S = -SID c gives (0, 0, SID)
+        const double t[3] = {0.0, 0.0, (double)g->sid};
+        const double R[3][3] = {{eu[0], eu[1], eu[2]}, {ev[0], ev[1], ev[2]}, {c[0], c[1], c[2]}};
+        float *P = mats + 12 * (size_t)k;
+        for (int a = 0; a < 3; ++a) {
+            P[a] = (float)(fu * R[0][a] + cu * R[2][a]);
+            P[4 + a] = (float)(fv * R[1][a] + cv * R[2][a]);
+            P[8 + a] = (float)R[2][a];
+        }
+        P[3] = (float)(fu * t[0] + cu * t[2]);
+        P[7] = (float)(fv * t[1] + cv * t[2]);
+        P[11] = (float)t[2];
+    }
+    return PH_OK;
+}
+
+int ph_project_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, int dtype,
+                     void *stream)
+{
+    return project2d(g, false, rv, img, sino, batch, dtype, stream);
+}
+
+int ph_project_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, int dtype,
+                     void *stream)
+{
+    return project2d(g, true, rv, img, sino, batch, dtype, stream);
+}
+
+int ph_backproject_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+                         void *stream)
+{
+    return backproject2d(g, false, rv, sino, img, batch, dtype, stream);
+}
+
+int ph_backproject_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+                         void *stream)
+{
+    return backproject2d(g, true, rv, sino, img, batch, dtype, stream);
+}
+
+int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch, int dtype,
+                      void *stream)
+{
+    if (!vol || !proj)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    const void *views = nullptr;
+    bool axial = false;
+    st = prep3d(g, mats, false, &G, &views, &axial);
+    if (st != PH_OK)
+        return st;
+    return to_status(
+        launch_project_cone(dtype, G, (const ConeFPView *)views, vol, proj, batch, (hipStream_t)stream));
+}
+
+int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch, int dtype,
+                          void *stream)
+{
+    if (!vol || !proj)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    const void *views = nullptr;
+    bool axial = false;
+    st = prep3d(g, mats, true, &G, &views, &axial);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, proj, false, vol, batch,
+                                             (hipStream_t)stream));
+}
+
+int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
+                        const float *W_red, int batch, int dtype, void *stream)
+{
+    return weight_filter2d(g, fan != 0, sino, out, K, M, W_red, batch, dtype, stream);
+}
+
+int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M, const float *W_red,
+                        const float *W, int batch, int dtype, void *stream)
+{
+    if (!proj || !out)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    st = make_geom3d(g, &G);
+    if (st != PH_OK)
+        return st;
+    st = filter_len(K, M, g->det_shape[1], &M);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(2, g->det_shape[1], g->det_shape[0], g->n_proj, batch, g->det_spacing[1], g->det_spacing[0],
+                     g->sid, g->sdd, g->angular_range, K, M, W_red, W, &a);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_weight_filter(dtype, a, proj, out, (hipStream_t)stream));
+}
+
+size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1)
+        return 0;
+    return round_up((size_t)batch * g->n_proj * g->det_shape * sizeof(float));
+}
+
+size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1)
+        return 0;
+    return round_up((size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1] * sizeof(float));
+}
+
+int ph_fbp_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    return fbp2d(g, false, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
+}
+
+int ph_fbp_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    return fbp2d(g, true, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
+}
+
+int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
+                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    if (!proj || !vol)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    std::vector<double> P;
+    st = validate3d(g, mats, &G, &P);
+    if (st != PH_OK)
+        return st;
+    if (!ws || ws_bytes < ph_workspace_bytes_3d(g, batch))
+        return PH_ERR_WORKSPACE;
+    st = filter_len(K, M, g->det_shape[1], &M);
+    if (st != PH_OK)
+        return st;
+    const void *views = nullptr;
+    bool axial = false;
+    st = upload3d(g, mats, P, true, &views, &axial);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(2, g->det_shape[1], g->det_shape[0], g->n_proj, batch, g->det_spacing[1], g->det_spacing[0],
+                     g->sid, g->sdd, g->angular_range, K, M, W_red, W, &a);
+    if (st != PH_OK)
+        return st;
+    float *q = (float *)ws;
+    st = to_status(launch_weight_filter(dtype, a, proj, q, (hipStream_t)stream));
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, q, true, vol, batch,
+                                             (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ph {
+
+// ------------------------------------------------------------- storage types
+// FP32 math everywhere; volumes and projections may be stored as FP16 or BF16
+// (round to nearest even on store).
+
+typedef _Float16 f16_t;
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float load_f32(const float *p) { return *p; }
+__device__ __forceinline__ float load_f32(const f16_t *p) { return (float)(*p); }
+__device__ __forceinline__ float load_f32(const bf16_t *p) { return __uint_as_float((uint32_t)p->bits << 16); }
+
+__device__ __forceinline__ void store_f32(float *p, float v) { *p = v; }
+__device__ __forceinline__ void store_f32(f16_t *p, float v) { *p = (f16_t)v; }
+__device__ __forceinline__ void store_f32(bf16_t *p, float v)
+{
+    uint32_t u = __float_as_uint(v);
+    uint16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        r = (uint16_t)((u >> 16) | 0x40u);  // NaN stays a (quiet) NaN
+    else
+        r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    p->bits = r;
+}
+
+// ----------------------------------------------------------- device geometry
+
+struct Geom2D {
+    int nx, ny, nu, n_proj;
+    float ox, oy;          // world mm of pixel (0,0)
+    float inv_sx, inv_sy;  // 1 / spacing
+    float sx, sy;
+    float du, cu;          // detector spacing, (nu-1)/2
+    float sid, sdd;
+    float step;            // ray sampling step (mm)
+    float dbeta;           // range / n_proj
+};
+
+struct Geom3D {
+    int nx, ny, nz, nu, nv, n_proj;
+    float ox, oy, oz;
+    float inv_sx, inv_sy, inv_sz;
+    float du, dv, cu, cv;
+    float sid, sdd;
+    float step;
+    float dbeta;
+};
+
+// Per-view parameters of the cone back-projector: rows mapping the centred
+// voxel index (x - (nx-1)/2, y - (ny-1)/2, z - (nz-1)/2, 1) to
+// (Uc, Vc, W) with Uc = (j - cu) W, Vc = (i - cv) W, W the depth in mm.
+struct ConeBPView {
+    float r[3][4];
+};
+
+// Per-view parameters of the cone forward projector (world mm, isocentre at
+// the origin): source s; the ray of centred pixel (jc, ic) has direction
+// d0 + jc*du + ic*dv (not normalised, pointing away from the source).
+struct ConeFPView {
+    float s[3];
+    float d0[3];
+    float du[3];
+    float dv[3];
+};
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.  `dtype`: 0 f32, 1 f16, 2 bf16.
+
+hipError_t launch_project_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *img, void *sino,
+                             int batch, hipStream_t stream);
+hipError_t launch_backproject_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
+                                 bool sino_is_f32, void *img, int batch, hipStream_t stream);
+hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const void *vol, void *proj,
+                               int batch, hipStream_t stream);
+hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial,
+                                   const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream);
+
+// Row filter: rows of length nu (count = batch * n_proj * nv) are weighted by
+// W_red[view][u] * W_cos[v][u] * W[v][u] (any of the three may be NULL; the
+// cosine weight is computed from sdd when cos_sdd > 0), filtered with the
+// real response K[M] (symmetrised) and written as FP32.
+struct FilterArgs {
+    int nu, nv, n_proj, batch, M, log2M;
+    float du, dv, cu, cv;
+    float cos_sdd;       // > 0: apply SDD / sqrt(SDD^2 + u^2 + v^2)
+    const float *K;      // device [M]
+    const float2 *tw;    // device [M/2] exp(-2 pi i t / M)
+    const float *W_red;  // device [n_proj][nu] or NULL
+    const float *W;      // device [nv][nu] or NULL
+};
+hipError_t launch_weight_filter(int dtype, const FilterArgs &a, const void *in, float *out, hipStream_t stream);
+
+}  // namespace ph

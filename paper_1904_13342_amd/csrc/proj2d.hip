@@ -1,0 +1,175 @@
+// 2D parallel- and fan-beam forward projection (ray-driven, one thread per
+// detector bin) and back-projection (voxel-driven, one thread per pixel),
+// Sec. II.B.2.  The images of the 2D workloads (at most 512 x 512 FP32,
+// 1 MiB) stay resident in L2, so both kernels read global memory directly.
+#include "common.h"
+
+namespace ph {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ float pix(const T *img, int nx, int ny, int ix, int iy)
+{
+    return (ix >= 0 && iy >= 0 && ix < nx && iy < ny) ? load_f32(img + (size_t)iy * nx + ix) : 0.0f;
+}
+
+// Ray of bin j in a view with central ray vector c: anchor a (point closest to
+// the isocentre) and unit direction d, world mm.
+template <bool FAN>
+__device__ __forceinline__ void ray2d(const Geom2D &g, float2 c, int j, float &ax, float &ay, float &dx, float &dy)
+{
+    const float ex = -c.y, ey = c.x;
+    const float u = ((float)j - g.cu) * g.du;
+    if (!FAN) {
+        ax = u * ex;
+        ay = u * ey;
+        dx = c.x;
+        dy = c.y;
+    } else {
+        const float sx = -g.sid * c.x, sy = -g.sid * c.y;
+        float tx = g.sdd * c.x + u * ex, ty = g.sdd * c.y + u * ey;  // detector point - source
+        const float rn = 1.0f / sqrtf(tx * tx + ty * ty);
+        dx = tx * rn;
+        dy = ty * rn;
+        const float t0 = -(sx * dx + sy * dy);
+        ax = fmaf(t0, dx, sx);
+        ay = fmaf(t0, dy, sy);
+    }
+}
+
+// Integer sample range covering the open box (-1, n) in index coordinates,
+// widened by one sample on each side (samples outside add exact zeros).
+__device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float &hi)
+{
+    if (fabsf(e) < 1e-30f)
+        return p > -1.0f && p < (float)n;
+    float t1 = (-1.0f - p) / e, t2 = ((float)n - p) / e;
+    lo = fmaxf(lo, fminf(t1, t2));
+    hi = fminf(hi, fmaxf(t1, t2));
+    return true;
+}
+
+template <typename T, bool FAN>
+__global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__restrict__ views,
+                                                   const T *__restrict__ img, T *__restrict__ sino)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const int b = blockIdx.z;
+    if (j >= g.nu)
+        return;
+    const T *im = img + (size_t)b * g.nx * g.ny;
+    float ax, ay, dx, dy;
+    ray2d<FAN>(g, views[k], j, ax, ay, dx, dy);
+    const float X0 = (ax - g.ox) * g.inv_sx, Y0 = (ay - g.oy) * g.inv_sy;
+    const float eX = g.step * dx * g.inv_sx, eY = g.step * dy * g.inv_sy;
+    float lo = -3.0e38f, hi = 3.0e38f;
+    float acc = 0.0f;
+    if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && lo < hi) {
+        const int k0 = (int)floorf(lo) - 1, k1 = (int)ceilf(hi) + 1;
+        for (int m = k0; m <= k1; ++m) {
+            const float fm = (float)m;
+            const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0);
+            const float fx = floorf(X), fy = floorf(Y);
+            const int ix = (int)fx, iy = (int)fy;
+            const float tx = X - fx, ty = Y - fy;
+            const float p00 = pix(im, g.nx, g.ny, ix, iy), p01 = pix(im, g.nx, g.ny, ix + 1, iy);
+            const float p10 = pix(im, g.nx, g.ny, ix, iy + 1), p11 = pix(im, g.nx, g.ny, ix + 1, iy + 1);
+            const float a0 = fmaf(tx, p01 - p00, p00), a1 = fmaf(tx, p11 - p10, p10);
+            acc += fmaf(ty, a1 - a0, a0);
+        }
+    }
+    store_f32(sino + ((size_t)b * g.n_proj + k) * g.nu + j, g.step * acc);
+}
+
+template <typename T, typename TI, bool FAN>
+__global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__restrict__ views,
+                                                   const TI *__restrict__ sino, T *__restrict__ img)
+{
+    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int b = blockIdx.z;
+    if (ix >= g.nx || iy >= g.ny)
+        return;
+    const TI *sb = sino + (size_t)b * g.n_proj * g.nu;
+    const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
+    const float rdu = 1.0f / g.du;
+    float acc = 0.0f;
+    for (int k = 0; k < g.n_proj; ++k) {
+        const float2 c = views[k];
+        const float xu = -x * c.y + y * c.x;
+        float su, wt;
+        if (!FAN) {
+            su = fmaf(xu, rdu, g.cu);
+            wt = 1.0f;
+        } else {
+            const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
+            const float rw = 1.0f / w;
+            su = fmaf(g.sdd * xu * rw, rdu, g.cu);
+            const float sw = g.sid * rw;
+            wt = sw * sw;
+        }
+        const float fu = floorf(su);
+        const int j = (int)fu;
+        const float t = su - fu;
+        const TI *row = sb + (size_t)k * g.nu;
+        const float p0 = (j >= 0 && j < g.nu) ? load_f32(row + j) : 0.0f;
+        const float p1 = (j + 1 >= 0 && j + 1 < g.nu) ? load_f32(row + j + 1) : 0.0f;
+        acc = fmaf(wt, fmaf(t, p1 - p0, p0), acc);
+    }
+    store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.dbeta * acc);
+}
+
+template <typename T>
+hipError_t fp2d(bool fan, const Geom2D &g, const float2 *views, const void *img, void *sino, int batch,
+                hipStream_t s)
+{
+    dim3 grid((g.nu + 255) / 256, g.n_proj, batch);
+    if (fan)
+        hipLaunchKernelGGL((fp2d_kernel<T, true>), grid, dim3(256), 0, s, g, views, (const T *)img, (T *)sino);
+    else
+        hipLaunchKernelGGL((fp2d_kernel<T, false>), grid, dim3(256), 0, s, g, views, (const T *)img, (T *)sino);
+    return hipGetLastError();
+}
+
+template <typename T, typename TI>
+hipError_t bp2d(bool fan, const Geom2D &g, const float2 *views, const void *sino, void *img, int batch,
+                hipStream_t s)
+{
+    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
+    if (fan)
+        hipLaunchKernelGGL((bp2d_kernel<T, TI, true>), grid, dim3(256), 0, s, g, views, (const TI *)sino,
+                           (T *)img);
+    else
+        hipLaunchKernelGGL((bp2d_kernel<T, TI, false>), grid, dim3(256), 0, s, g, views, (const TI *)sino,
+                           (T *)img);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *img, void *sino,
+                             int batch, hipStream_t stream)
+{
+    switch (dtype) {
+    case 0: return fp2d<float>(fan, g, views, img, sino, batch, stream);
+    case 1: return fp2d<f16_t>(fan, g, views, img, sino, batch, stream);
+    default: return fp2d<bf16_t>(fan, g, views, img, sino, batch, stream);
+    }
+}
+
+hipError_t launch_backproject_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
+                                 bool sino_is_f32, void *img, int batch, hipStream_t stream)
+{
+    switch (dtype) {
+    case 0: return bp2d<float, float>(fan, g, views, sino, img, batch, stream);
+    case 1:
+        return sino_is_f32 ? bp2d<f16_t, float>(fan, g, views, sino, img, batch, stream)
+                           : bp2d<f16_t, f16_t>(fan, g, views, sino, img, batch, stream);
+    default:
+        return sino_is_f32 ? bp2d<bf16_t, float>(fan, g, views, sino, img, batch, stream)
+                           : bp2d<bf16_t, bf16_t>(fan, g, views, sino, img, batch, stream);
+    }
+}
+
+}  // namespace ph

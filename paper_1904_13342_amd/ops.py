@@ -1,0 +1,283 @@
+"""Python binding of the C ABI (include/pyrohip.h), one function per entry
+point with the same name minus the ``ph_`` prefix.
+
+Argument marshalling only: tensors must already live on the GPU; shapes are
+checked against the geometry here (the C ABI sees plain pointers), outputs
+are allocated with torch, and the work is enqueued on torch's current HIP
+stream.  Every operator runs in the HIP kernels of libpyrohip.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from ._lib import Geom2D, Geom3D, PH_BF16, PH_F16, PH_F32, check, lib
+
+_DTYPES = {torch.float32: PH_F32, torch.float16: PH_F16, torch.bfloat16: PH_BF16}
+
+
+# ------------------------------------------------------------------ geometry
+
+def geom2d(vol_shape, vol_spacing, det_shape, det_spacing, n_proj, angular_range, sid=0.0, sdd=0.0, step_mm=0.0,
+           vol_origin=None):
+    """ph_geom2d record; shapes/spacings in (y, x) order; origin defaults to a
+    grid centred on the rotation axis."""
+    g = Geom2D()
+    vol_shape = tuple(int(v) for v in vol_shape)
+    vol_spacing = tuple(float(v) for v in vol_spacing)
+    if vol_origin is None:
+        vol_origin = tuple(-(n - 1) / 2.0 * s for n, s in zip(vol_shape, vol_spacing))
+    g.vol_shape[:] = vol_shape
+    g.vol_spacing[:] = vol_spacing
+    g.vol_origin[:] = tuple(float(v) for v in vol_origin)
+    g.det_shape = int(det_shape[0] if isinstance(det_shape, (tuple, list)) else det_shape)
+    g.det_spacing = float(det_spacing[0] if isinstance(det_spacing, (tuple, list)) else det_spacing)
+    g.n_proj = int(n_proj)
+    g.angular_range = float(angular_range)
+    g.sid, g.sdd, g.step_mm = float(sid), float(sdd), float(step_mm)
+    return g
+
+
+def geom3d(vol_shape, vol_spacing, det_shape, det_spacing, n_proj, angular_range, sid, sdd, step_mm=0.0,
+           vol_origin=None):
+    """ph_geom3d record; volume in (z, y, x) order, detector in (v, u) order."""
+    g = Geom3D()
+    vol_shape = tuple(int(v) for v in vol_shape)
+    vol_spacing = tuple(float(v) for v in vol_spacing)
+    if vol_origin is None:
+        vol_origin = tuple(-(n - 1) / 2.0 * s for n, s in zip(vol_shape, vol_spacing))
+    g.vol_shape[:] = vol_shape
+    g.vol_spacing[:] = vol_spacing
+    g.vol_origin[:] = tuple(float(v) for v in vol_origin)
+    g.det_shape[:] = tuple(int(v) for v in det_shape)
+    g.det_spacing[:] = tuple(float(v) for v in det_spacing)
+    g.n_proj = int(n_proj)
+    g.angular_range = float(angular_range)
+    g.sid, g.sdd, g.step_mm = float(sid), float(sdd), float(step_mm)
+    return g
+
+
+def from_spec(spec):
+    """Geometry record from any object with the attributes kind, vol_shape,
+    vol_spacing, det_shape, det_spacing, n_proj, angular_range, sid, sdd,
+    step_mm (and optionally vol_origin)."""
+    origin = getattr(spec, "vol_origin", None)
+    if spec.kind == "cone3d":
+        return geom3d(spec.vol_shape, spec.vol_spacing, spec.det_shape, spec.det_spacing, spec.n_proj,
+                      spec.angular_range, spec.sid, spec.sdd, spec.step_mm, origin)
+    return geom2d(spec.vol_shape, spec.vol_spacing, spec.det_shape, spec.det_spacing, spec.n_proj,
+                  spec.angular_range, spec.sid, spec.sdd, spec.step_mm, origin)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def ray_vectors_2d(g):
+    out = np.empty((g.n_proj, 2), dtype=np.float32)
+    check("ph_ray_vectors_2d", lib().ph_ray_vectors_2d(ctypes.byref(g), _fptr(out)))
+    return out
+
+
+def projection_matrices_3d(g):
+    out = np.empty((g.n_proj, 3, 4), dtype=np.float32)
+    check("ph_projection_matrices_3d", lib().ph_projection_matrices_3d(ctypes.byref(g), _fptr(out)))
+    return out
+
+
+# --------------------------------------------------------------- marshalling
+
+def _host_traj(traj, shape):
+    a = np.ascontiguousarray(np.asarray(traj, dtype=np.float32))
+    if a.shape != shape:
+        raise ValueError(f"trajectory has shape {a.shape}, expected {shape}")
+    return a
+
+
+def _dev(t, name, expect_tail):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype not in _DTYPES:
+        raise ValueError(f"{name} has unsupported dtype {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    tail = tuple(t.shape[-len(expect_tail):]) if t.dim() >= len(expect_tail) else None
+    if tail != tuple(expect_tail) or t.dim() not in (len(expect_tail), len(expect_tail) + 1):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [B,] {tuple(expect_tail)}")
+    batch = 1 if t.dim() == len(expect_tail) else t.shape[0]
+    if batch < 1:
+        raise ValueError(f"{name} has an empty batch")
+    return batch
+
+
+def _f32_dev(t, name, n):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 GPU tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+    return t.data_ptr()
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _vol_tail(g):
+    return tuple(g.vol_shape)
+
+
+def _sino_tail(g):
+    if isinstance(g, Geom3D):
+        return (g.n_proj, g.det_shape[0], g.det_shape[1])
+    return (g.n_proj, g.det_shape)
+
+
+def _traj(g, traj):
+    if isinstance(g, Geom3D):
+        return _host_traj(traj, (g.n_proj, 3, 4))
+    return _host_traj(traj, (g.n_proj, 2))
+
+
+def _unary(fn, g, traj, x, in_tail, out_tail, out=None):
+    batch = _dev(x, "input", in_tail)
+    t = _traj(g, traj)
+    shape = (tuple(x.shape[:1]) if x.dim() == len(in_tail) + 1 else ()) + tuple(out_tail)
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out has the wrong shape, dtype, device or layout")
+    status = getattr(lib(), fn)(ctypes.byref(g), _fptr(t), ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), batch, _DTYPES[x.dtype], _stream(x))
+    check(fn, status)
+    return out
+
+
+# ----------------------------------------------------------------- operators
+
+def project_par2d(g, ray_vecs, img, out=None):
+    return _unary("ph_project_par2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+
+
+def project_fan2d(g, ray_vecs, img, out=None):
+    return _unary("ph_project_fan2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+
+
+def project_cone3d(g, mats, vol, out=None):
+    return _unary("ph_project_cone3d", g, mats, vol, _vol_tail(g), _sino_tail(g), out)
+
+
+def backproject_par2d(g, ray_vecs, sino, out=None):
+    return _unary("ph_backproject_par2d", g, ray_vecs, sino, _sino_tail(g), _vol_tail(g), out)
+
+
+def backproject_fan2d(g, ray_vecs, sino, out=None):
+    return _unary("ph_backproject_fan2d", g, ray_vecs, sino, _sino_tail(g), _vol_tail(g), out)
+
+
+def backproject_cone3d(g, mats, proj, out=None):
+    return _unary("ph_backproject_cone3d", g, mats, proj, _sino_tail(g), _vol_tail(g), out)
+
+
+def _filter_len(K, M):
+    if K is not None:
+        return K.numel() if M in (None, 0) else M
+    return 0 if M is None else M
+
+
+def weight_filter_2d(g, sino, fan, K=None, M=None, W_red=None, out=None):
+    batch = _dev(sino, "sino", _sino_tail(g))
+    M = _filter_len(K, M)
+    shape = tuple(sino.shape)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=sino.device)
+    status = lib().ph_weight_filter_2d(ctypes.byref(g), int(bool(fan)), ctypes.c_void_p(sino.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _f32_dev(K, "K", M), M,
+                                       _f32_dev(W_red, "W_red", g.n_proj * g.det_shape), batch,
+                                       _DTYPES[sino.dtype], _stream(sino))
+    check("ph_weight_filter_2d", status)
+    return out
+
+
+def weight_filter_3d(g, proj, K=None, M=None, W_red=None, W=None, out=None):
+    batch = _dev(proj, "proj", _sino_tail(g))
+    M = _filter_len(K, M)
+    nv, nu = g.det_shape[0], g.det_shape[1]
+    if out is None:
+        out = torch.empty(tuple(proj.shape), dtype=torch.float32, device=proj.device)
+    status = lib().ph_weight_filter_3d(ctypes.byref(g), ctypes.c_void_p(proj.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _f32_dev(K, "K", M), M,
+                                       _f32_dev(W_red, "W_red", g.n_proj * nu), _f32_dev(W, "W", nv * nu), batch,
+                                       _DTYPES[proj.dtype], _stream(proj))
+    check("ph_weight_filter_3d", status)
+    return out
+
+
+def workspace_bytes_2d(g, batch=1):
+    return int(lib().ph_workspace_bytes_2d(ctypes.byref(g), int(batch)))
+
+
+def workspace_bytes_3d(g, batch=1):
+    return int(lib().ph_workspace_bytes_3d(ctypes.byref(g), int(batch)))
+
+
+def _fbp2d(fn, g, ray_vecs, sino, K, M, W_red, out, ws):
+    batch = _dev(sino, "sino", _sino_tail(g))
+    t = _traj(g, ray_vecs)
+    M = _filter_len(K, M)
+    shape = (tuple(sino.shape[:1]) if sino.dim() == 3 else ()) + _vol_tail(g)
+    if out is None:
+        out = torch.empty(shape, dtype=sino.dtype, device=sino.device)
+    nbytes = workspace_bytes_2d(g, batch)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=sino.device)
+    status = getattr(lib(), fn)(ctypes.byref(g), _fptr(t), ctypes.c_void_p(sino.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), _f32_dev(K, "K", M), M,
+                                _f32_dev(W_red, "W_red", g.n_proj * g.det_shape), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel() * ws.element_size(), batch, _DTYPES[sino.dtype], _stream(sino))
+    check(fn, status)
+    return out
+
+
+def fbp_par2d(g, ray_vecs, sino, K=None, M=None, W_red=None, out=None, ws=None):
+    return _fbp2d("ph_fbp_par2d", g, ray_vecs, sino, K, M, W_red, out, ws)
+
+
+def fbp_fan2d(g, ray_vecs, sino, K=None, M=None, W_red=None, out=None, ws=None):
+    return _fbp2d("ph_fbp_fan2d", g, ray_vecs, sino, K, M, W_red, out, ws)
+
+
+def fdk_cone3d(g, mats, proj, K=None, M=None, W_red=None, W=None, out=None, ws=None):
+    batch = _dev(proj, "proj", _sino_tail(g))
+    t = _traj(g, mats)
+    M = _filter_len(K, M)
+    nv, nu = g.det_shape[0], g.det_shape[1]
+    shape = (tuple(proj.shape[:1]) if proj.dim() == 4 else ()) + _vol_tail(g)
+    if out is None:
+        out = torch.empty(shape, dtype=proj.dtype, device=proj.device)
+    nbytes = workspace_bytes_3d(g, batch)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=proj.device)
+    status = lib().ph_fdk_cone3d(ctypes.byref(g), _fptr(t), ctypes.c_void_p(proj.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), _f32_dev(K, "K", M), M,
+                                 _f32_dev(W_red, "W_red", g.n_proj * nu), _f32_dev(W, "W", nv * nu),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), batch,
+                                 _DTYPES[proj.dtype], _stream(proj))
+    check("ph_fdk_cone3d", status)
+    return out
+
+
+def version():
+    return lib().ph_version().decode()
+
+
+__all__ = [
+    "geom2d", "geom3d", "from_spec", "ray_vectors_2d", "projection_matrices_3d", "project_par2d",
+    "project_fan2d", "project_cone3d", "backproject_par2d", "backproject_fan2d", "backproject_cone3d",
+    "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
+    "fbp_fan2d", "fdk_cone3d", "version",
+]
