@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the known-operator CT hot path on one MI355X.
+
+One step = the whole path over one synthetic 512^3 cone-beam workload
+(12 seeded random ellipsoids at 0.5 mm, 360 views over 360 deg, 1024 x 768
+detector at 0.8 mm, SID 750 mm, SDD 1200 mm), resident in HBM:
+
+    forward projection  vol -> proj                 (ph_project_cone3d)
+    weighting + Ram-Lak row filter  proj -> q       (ph_weight_filter_3d)
+    back-projection  q -> vol_rec                   (ph_backproject_cone3d)
+
+The last two are exactly ph_fdk_cone3d, called as its two stages so that each
+kernel is timed with HIP events on the stream it runs on.  The JSON line
+reports back-projection GUPS (voxel-view updates per second of the FDK
+stage), forward-projection Gsamples/s, a roofline entry for the dominant
+kernel and for each kernel, and the FP64 oracle timed on a bounded sample on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X figures: 256 CUs at 2.4 GHz, 64 FP32 lanes per CU per clock without
+# packed math; HBM3E 8 TB/s.
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
+PEAK_HBM_GBS = 8000.0
+# Algorithmic lane-ops per unit of work (kernel table).
+OPS_PER_UPDATE = 11.0      # back-projection: v coordinate, floor/fract, 3 lerps, accumulate
+OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7 lerps, accumulate
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cone3d_512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def count_samples(spec, device):
+    """Number of ray samples inside the open index box (-1, N)^3: for every
+    ray, the integers k strictly between the entry and exit parameters of
+    the line a + k*step*d through that box (a = point of the ray closest to
+    the isocentre, d unit direction).  Computed in float64 with torch."""
+    import torch
+    nz, ny, nx = spec.vol_shape
+    sz, sy, sx = spec.vol_spacing
+    oz, oy, ox = spec.origin
+    nv, nu = spec.det_shape
+    dv, du = spec.det_spacing
+    u = (torch.arange(nu, dtype=torch.float64, device=device) - (nu - 1) / 2) * du
+    v = (torch.arange(nv, dtype=torch.float64, device=device) - (nv - 1) / 2) * dv
+    V, U = torch.meshgrid(v, u, indexing="ij")
+    total = 0
+    for k in range(spec.n_proj):
+        b = spec.angular_range * k / spec.n_proj
+        c = (math.cos(b), math.sin(b))
+        e = (-math.sin(b), math.cos(b))
+        src = (-spec.sid * c[0], -spec.sid * c[1], 0.0)
+        dx = spec.sdd * c[0] + U * e[0]
+        dy = spec.sdd * c[1] + U * e[1]
+        dz = V
+        n = torch.sqrt(dx * dx + dy * dy + dz * dz)
+        dx, dy, dz = dx / n, dy / n, dz / n
+        t0 = -(src[0] * dx + src[1] * dy)
+        lo = torch.full_like(U, -math.inf)
+        hi = torch.full_like(U, math.inf)
+        ok = torch.ones_like(U, dtype=torch.bool)
+        for a, d, o, s, N in ((src[0], dx, ox, sx, nx), (src[1], dy, oy, sy, ny), (0.0, dz, oz, sz, nz)):
+            p0 = (a + t0 * d - o) / s
+            ee = spec.step * d / s
+            nonzero = ee.abs() > 1e-300
+            safe = torch.where(nonzero, ee, torch.ones_like(ee))
+            t1 = (-1.0 - p0) / safe
+            t2 = (N - p0) / safe
+            lo = torch.where(nonzero, torch.maximum(lo, torch.minimum(t1, t2)), lo)
+            hi = torch.where(nonzero, torch.minimum(hi, torch.maximum(t1, t2)), hi)
+            ok &= nonzero | ((p0 > -1.0) & (p0 < N))
+        cnt = torch.clamp(torch.ceil(hi) - torch.floor(lo) - 1.0, min=0.0)
+        total += int(torch.where(ok & (hi > lo), cnt, torch.zeros_like(cnt)).sum().item())
+    return total
+
+
+def cpu_baseline(spec, vol_host, target_s):
+    """The FP64 oracle on a bounded sample of the same workload: back-projection
+    of a set of z slices (all views) and forward projection of a set of views.
+    Rates are per second of wall time on all host cores."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    nz = spec.vol_shape[0]
+    nvox_slice = spec.vol_shape[1] * spec.vol_shape[2]
+    q = np.zeros((spec.n_proj,) + tuple(spec.det_shape))
+    # calibrate on one slice, then size the sample to ~target_s/2 of back-projection
+    t = time.perf_counter()
+    oracle.backproject(spec, q, slices=[nz // 2])
+    per_slice = max(time.perf_counter() - t, 1e-3)
+    n_sl = int(max(1, min(nz, (0.5 * target_s) / per_slice)))
+    slices = sorted(set(int(round(x)) for x in np.linspace(0, nz - 1, n_sl)))
+    rng = np.random.default_rng(0)
+    q = rng.standard_normal((spec.n_proj,) + tuple(spec.det_shape)).astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    oracle.backproject(spec, q, slices=slices)
+    t_bp = time.perf_counter() - t
+    bp_gups = len(slices) * nvox_slice * spec.n_proj / t_bp / 1e9
+    # forward projection: calibrate on one view, then ~target_s/2
+    f = vol_host.astype(np.float64)
+    t = time.perf_counter()
+    oracle.project(spec, f, views=[0])
+    per_view = max(time.perf_counter() - t, 1e-3)
+    n_v = int(max(1, min(spec.n_proj, (0.5 * target_s) / per_view)))
+    views = sorted(set(int(round(x)) for x in np.linspace(0, spec.n_proj - 1, n_v)))
+    t = time.perf_counter()
+    oracle.project(spec, f, views=views)
+    t_fp = time.perf_counter() - t
+    samples = oracle.count_samples(spec, views=views)
+    return {
+        "value": bp_gups,
+        "unit": "GUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle back-projection of {len(slices)} of {nz} z-slices over all {spec.n_proj} views "
+                   f"({t_bp:.1f} s) and forward projection of {len(views)} of {spec.n_proj} views ({t_fp:.1f} s)"),
+        "fp_gsamples_per_s": samples / t_fp / 1e9,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); see DESIGN.md for how the path "
+              "would shard across GPUs.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1904_13342_amd as ph
+    import synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.config(args.config)
+    g = ph.from_spec(spec)
+    mats = ph.projection_matrices_3d(g)
+    prm = synth.random_ellipsoids(spec.seed, spec.n_figures, spec.vol_shape, spec.vol_spacing)
+    vol = synth.rasterize_ellipsoids(prm, spec.vol_shape, spec.vol_spacing, sub=1, device=dev,
+                                     dtype=torch.float32).contiguous()
+    proj = torch.empty((spec.n_proj,) + tuple(spec.det_shape), dtype=torch.float32, device=dev)
+    q = torch.empty_like(proj)
+    rec = torch.empty_like(vol)
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        ph.project_cone3d(g, mats, vol, out=proj)
+        if ev is not None:
+            ev[1].record()
+        ph.weight_filter_3d(g, proj, out=q)
+        if ev is not None:
+            ev[2].record()
+        ph.backproject_cone3d(g, mats, q, out=rec)
+        if ev is not None:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fp_ms = np.mean([e[0].elapsed_time(e[1]) for e in events])
+    wf_ms = np.mean([e[1].elapsed_time(e[2]) for e in events])
+    bp_ms = np.mean([e[2].elapsed_time(e[3]) for e in events])
+    ms_per_step = wall * 1e3 / args.steps
+
+    nz, ny, nx = spec.vol_shape
+    nv, nu = spec.det_shape
+    updates = nx * ny * nz * spec.n_proj
+    samples = count_samples(spec, dev)
+    fdk_ms = wf_ms + bp_ms
+    bp_gups = updates / (bp_ms * 1e-3) / 1e9
+    fdk_gups = updates / (fdk_ms * 1e-3) / 1e9
+    fp_gsps = samples / (fp_ms * 1e-3) / 1e9
+    wf_bytes = 2 * 4 * spec.n_proj * nv * nu + 4 * spec.n_proj * nu
+
+    kernels = {
+        "fp_cone": {"bound": "alu", "ms": fp_ms, "achieved": OPS_PER_SAMPLE * samples / (fp_ms * 1e-3) / 1e12,
+                    "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "units_per_launch": samples,
+                    "unit_name": "ray samples", "ops_per_unit": OPS_PER_SAMPLE},
+        "weight_filter": {"bound": "hbm", "ms": wf_ms, "achieved": wf_bytes / (wf_ms * 1e-3) / 1e9,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "units_per_launch": wf_bytes,
+                          "unit_name": "bytes"},
+        "bp_cone": {"bound": "alu", "ms": bp_ms, "achieved": OPS_PER_UPDATE * updates / (bp_ms * 1e-3) / 1e12,
+                    "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "units_per_launch": updates,
+                    "unit_name": "voxel-view updates", "ops_per_unit": OPS_PER_UPDATE},
+    }
+    for kv in kernels.values():
+        kv["frac"] = kv["achieved"] / kv["peak"]
+    dom_name = max(kernels, key=lambda n: kernels[n]["ms"])
+    dom = kernels[dom_name]
+    roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                "unit": dom["unit"], "frac": dom["frac"], "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(spec, vol.cpu().numpy(), args.cpu_seconds)
+
+    line = {
+        "metric": "cone-beam backprojection GUPS + forward-proj Gsamples/s at 512^3; %HBM roofline",
+        "value": fdk_gups,
+        "unit": "GUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: 12 seeded random ellipsoids, resident in HBM",
+        "config": {"workload": f"{spec.kind} {nx}x{ny}x{nz} at {spec.vol_spacing[0]} mm, {spec.n_proj} views over "
+                               f"{round(math.degrees(spec.angular_range))} deg, {nu}x{nv} detector at "
+                               f"{spec.det_spacing[0]} mm, SID {spec.sid:g}, SDD {spec.sdd:g}",
+                   "batch": 1, "step": "forward projection + weighting/Ram-Lak filter + back-projection"},
+        "bp_gups": bp_gups,
+        "fdk_gups": fdk_gups,
+        "fp_gsamples_per_s": fp_gsps,
+        "fp_ms": fp_ms,
+        "weight_filter_ms": wf_ms,
+        "bp_ms": bp_ms,
+        "fp_samples": samples,
+        "bp_updates": updates,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

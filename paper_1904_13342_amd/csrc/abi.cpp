@@ -143,6 +143,9 @@ int make_geom3d(const ph_geom3d *g, Geom3D *o)
     o->oz = g->vol_origin[0];
     o->oy = g->vol_origin[1];
     o->ox = g->vol_origin[2];
+    o->sz = g->vol_spacing[0];
+    o->sy = g->vol_spacing[1];
+    o->sx = g->vol_spacing[2];
     o->inv_sz = (float)(1.0 / g->vol_spacing[0]);
     o->inv_sy = (float)(1.0 / g->vol_spacing[1]);
     o->inv_sx = (float)(1.0 / g->vol_spacing[2]);
@@ -279,10 +282,10 @@ void fp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
         }
         ConeFPView &v = (*out)[(size_t)k];
         for (int r = 0; r < 3; ++r) {
-            v.s[r] = (float)S[r];
-            v.d0[r] = (float)d0[r];
-            v.du[r] = (float)du[r];
-            v.dv[r] = (float)dv[r];
+            v.s[r] = S[r];
+            v.d0[r] = d0[r];
+            v.du[r] = du[r];
+            v.dv[r] = dv[r];
         }
     }
 }

@@ -49,6 +49,7 @@ struct Geom2D {
 struct Geom3D {
     int nx, ny, nz, nu, nv, n_proj;
     float ox, oy, oz;
+    float sx, sy, sz;
     float inv_sx, inv_sy, inv_sz;
     float du, dv, cu, cv;
     float sid, sdd;
@@ -66,11 +67,13 @@ struct ConeBPView {
 // Per-view parameters of the cone forward projector (world mm, isocentre at
 // the origin): source s; the ray of centred pixel (jc, ic) has direction
 // d0 + jc*du + ic*dv (not normalised, pointing away from the source).
+// Double precision: the source sits ~SID from the volume, so an FP32 ray
+// direction would misplace the ray by ~SID * 2^-24 at the volume.
 struct ConeFPView {
-    float s[3];
-    float d0[3];
-    float du[3];
-    float dv[3];
+    double s[3];
+    double d0[3];
+    double du[3];
+    double dv[3];
 };
 
 // ------------------------------------------------------------------ launchers

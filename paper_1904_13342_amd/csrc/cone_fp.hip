@@ -35,21 +35,25 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     const int k = blockIdx.z % g.n_proj, b = blockIdx.z / g.n_proj;
     if (j >= g.nu || i >= g.nv)
         return;
-    const ConeFPView v = views[k];
-    const float jc = (float)j - g.cu, ic = (float)i - g.cv;
-    float d[3];
+    // ray setup in double precision: anchor (point closest to the isocentre)
+    // and unit direction, then index coordinates rounded once to FP32
+    const ConeFPView &v = views[k];
+    const double jc = (double)j - (double)g.cu, ic = (double)i - (double)g.cv;
+    double d[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-        d[t] = fmaf(jc, v.du[t], fmaf(ic, v.dv[t], v.d0[t]));
-    const float rn = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        d[t] = fma(jc, v.du[t], fma(ic, v.dv[t], v.d0[t]));
+    const double rn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 #pragma unroll
     for (int t = 0; t < 3; ++t)
         d[t] *= rn;
-    const float t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
-    const float X0 = (fmaf(t0, d[0], v.s[0]) - g.ox) * g.inv_sx;
-    const float Y0 = (fmaf(t0, d[1], v.s[1]) - g.oy) * g.inv_sy;
-    const float Z0 = (fmaf(t0, d[2], v.s[2]) - g.oz) * g.inv_sz;
-    const float eX = g.step * d[0] * g.inv_sx, eY = g.step * d[1] * g.inv_sy, eZ = g.step * d[2] * g.inv_sz;
+    const double t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
+    const float X0 = (float)((fma(t0, d[0], v.s[0]) - (double)g.ox) / (double)g.sx);
+    const float Y0 = (float)((fma(t0, d[1], v.s[1]) - (double)g.oy) / (double)g.sy);
+    const float Z0 = (float)((fma(t0, d[2], v.s[2]) - (double)g.oz) / (double)g.sz);
+    const float eX = (float)((double)g.step * d[0] / (double)g.sx);
+    const float eY = (float)((double)g.step * d[1] / (double)g.sy);
+    const float eZ = (float)((double)g.step * d[2] / (double)g.sz);
     float lo = -3.0e38f, hi = 3.0e38f;
     float acc = 0.0f;
     const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;

@@ -14,26 +14,29 @@ __device__ __forceinline__ float pix(const T *img, int nx, int ny, int ix, int i
 }
 
 // Ray of bin j in a view with central ray vector c: anchor a (point closest to
-// the isocentre) and unit direction d, world mm.
+// the isocentre) and unit direction d, world mm.  Fan rays are set up in
+// double precision: the source sits ~SID from the image, so an FP32 direction
+// would misplace the ray by ~SID * 2^-24 there.
 template <bool FAN>
-__device__ __forceinline__ void ray2d(const Geom2D &g, float2 c, int j, float &ax, float &ay, float &dx, float &dy)
+__device__ __forceinline__ void ray2d(const Geom2D &g, float2 c, int j, double &ax, double &ay, double &dx,
+                                      double &dy)
 {
-    const float ex = -c.y, ey = c.x;
-    const float u = ((float)j - g.cu) * g.du;
+    const double cx = c.x, cy = c.y, ex = -cy, ey = cx;
+    const double u = ((double)j - (double)g.cu) * (double)g.du;
     if (!FAN) {
         ax = u * ex;
         ay = u * ey;
-        dx = c.x;
-        dy = c.y;
+        dx = cx;
+        dy = cy;
     } else {
-        const float sx = -g.sid * c.x, sy = -g.sid * c.y;
-        float tx = g.sdd * c.x + u * ex, ty = g.sdd * c.y + u * ey;  // detector point - source
-        const float rn = 1.0f / sqrtf(tx * tx + ty * ty);
+        const double sx = -(double)g.sid * cx, sy = -(double)g.sid * cy;
+        const double tx = (double)g.sdd * cx + u * ex, ty = (double)g.sdd * cy + u * ey;  // detector - source
+        const double rn = 1.0 / sqrt(tx * tx + ty * ty);
         dx = tx * rn;
         dy = ty * rn;
-        const float t0 = -(sx * dx + sy * dy);
-        ax = fmaf(t0, dx, sx);
-        ay = fmaf(t0, dy, sy);
+        const double t0 = -(sx * dx + sy * dy);
+        ax = fma(t0, dx, sx);
+        ay = fma(t0, dy, sy);
     }
 }
 
@@ -59,10 +62,10 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
     if (j >= g.nu)
         return;
     const T *im = img + (size_t)b * g.nx * g.ny;
-    float ax, ay, dx, dy;
+    double ax, ay, dx, dy;
     ray2d<FAN>(g, views[k], j, ax, ay, dx, dy);
-    const float X0 = (ax - g.ox) * g.inv_sx, Y0 = (ay - g.oy) * g.inv_sy;
-    const float eX = g.step * dx * g.inv_sx, eY = g.step * dy * g.inv_sy;
+    const float X0 = (float)((ax - (double)g.ox) / (double)g.sx), Y0 = (float)((ay - (double)g.oy) / (double)g.sy);
+    const float eX = (float)((double)g.step * dx / (double)g.sx), eY = (float)((double)g.step * dy / (double)g.sy);
     float lo = -3.0e38f, hi = 3.0e38f;
     float acc = 0.0f;
     if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && lo < hi) {
