@@ -82,7 +82,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
-                f"libpyrohip.so not found at {LIB_PATH}; build it with `python -m paper_1904_13342_amd.build`")
+                f"libpyrohip.so not found at {LIB_PATH}; build it with `python paper_1904_13342_amd/build.py`")
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(handle, name)

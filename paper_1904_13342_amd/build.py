@@ -1,6 +1,8 @@
 """Build libpyrohip.so for gfx950 with hipcc (in-tree, no JIT cache).
 
-    python -m paper_1904_13342_amd.build
+    python paper_1904_13342_amd/build.py
+
+Run it as a script (importing the package loads the library it builds).
 """
 from __future__ import annotations
 

@@ -260,6 +260,32 @@ void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
     }
 }
 
+// Deepest column segment (64, 32 or 16 voxels) whose 16 x 16 x NZ brick
+// footprint fits the back-projector's 64 x 128 pixel LDS tile, from a bound on
+// the magnification (nearest approach of a voxel to the source) and on the
+// row slope across a brick at the top and bottom of the volume.
+int bp_segment(const ph_geom3d *g)
+{
+    const double sz = g->vol_spacing[0], sy = g->vol_spacing[1], sx = g->vol_spacing[2];
+    const double R = 0.5 * std::sqrt(std::pow((g->vol_shape[2] + 1) * sx, 2) + std::pow((g->vol_shape[1] + 1) * sy, 2));
+    double zmax = 0.0;
+    for (int e = -1; e <= g->vol_shape[0]; e += g->vol_shape[0] + 1)
+        zmax = std::fmax(zmax, std::fabs(g->vol_origin[0] + e * sz));
+    const double wmin = g->sid - R;
+    if (!(wmin > 0.0))
+        return 16;
+    const double mag = g->sdd / wmin;
+    const double brick = 16.0 * std::sqrt(2.0) * std::fmax(sx, sy);
+    const double tw = brick * mag / g->det_spacing[1] + 4.0;
+    const double slope = zmax * g->sdd / g->det_spacing[0] * brick / (wmin * wmin);
+    for (int nz = 64; nz >= 32; nz /= 2) {
+        const double th = nz * sz * mag / g->det_spacing[0] + slope + 4.0;
+        if (tw <= 64.0 && th <= 128.0)
+            return nz;
+    }
+    return 16;
+}
+
 // Forward-projector rays: source S = -M^-1 p4 and the direction
 // M^-1 (j, i, 1) written around the detector centre.
 void fp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeFPView> *out)
@@ -348,8 +374,8 @@ const float2 *twiddle_table(int M, int *st)
     return (const float2 *)cached(
         key,
         [&] {
-            std::vector<float2> t((size_t)M / 2);
-            for (int n = 0; n < M / 2; ++n)
+            std::vector<float2> t((size_t)M);
+            for (int n = 0; n < M; ++n)
                 t[(size_t)n] = make_float2((float)std::cos(2.0 * kPi * n / M), (float)-std::sin(2.0 * kPi * n / M));
             return as_bytes(t);
         },
@@ -751,8 +777,8 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
     st = prep3d(g, mats, true, &G, &views, &axial);
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, proj, false, vol, batch,
-                                             (hipStream_t)stream));
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), proj, false,
+                                             vol, batch, (hipStream_t)stream));
 }
 
 int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
@@ -846,8 +872,8 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
     st = to_status(launch_weight_filter(dtype, a, proj, q, (hipStream_t)stream));
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, q, true, vol, batch,
-                                             (hipStream_t)stream));
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), q, true, vol,
+                                             batch, (hipStream_t)stream));
 }
 
 }  // extern "C"

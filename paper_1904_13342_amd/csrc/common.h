@@ -85,7 +85,9 @@ hipError_t launch_backproject_2d(int dtype, bool fan, const Geom2D &g, const flo
                                  bool sino_is_f32, void *img, int batch, hipStream_t stream);
 hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const void *vol, void *proj,
                                int batch, hipStream_t stream);
-hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial,
+// nz_seg: voxels per thread column segment (16, 32 or 64), chosen by the host
+// so that a brick's detector footprint fits the LDS tile (64 x 128 pixels).
+hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
                                    const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream);
 
 // Row filter: rows of length nu (count = batch * n_proj * nv) are weighted by
@@ -97,7 +99,7 @@ struct FilterArgs {
     float du, dv, cu, cv;
     float cos_sdd;       // > 0: apply SDD / sqrt(SDD^2 + u^2 + v^2)
     const float *K;      // device [M]
-    const float2 *tw;    // device [M/2] exp(-2 pi i t / M)
+    const float2 *tw;    // device [M] exp(-2 pi i t / M)
     const float *W_red;  // device [n_proj][nu] or NULL
     const float *W;      // device [nv][nu] or NULL
 };

@@ -1,12 +1,15 @@
 // Voxel-driven, distance-weighted cone-beam back-projection from projection
 // matrices (Sec. II.B.2; Eq. 5's A^T in the FDK network).
 //
-// Mapping: a workgroup owns a 16 x 16 x NZ brick of voxels; each thread owns
+// Mapping: a workgroup owns a 16 x 16 x NZ brick of voxels (NZ = 16, 32 or
+// 64, the deepest whose footprint fits the LDS tile); each thread owns
 // one (x, y) column segment of NZ voxels and accumulates it in registers over
 // all views, so the volume is written exactly once.  Per view, the brick's
 // footprint on the detector (bounded by the projections of its 8 corners,
 // plus a one-pixel margin) is staged in LDS with zero outside the detector;
-// the bilinear fetches then come from LDS instead of texture units.
+// the bilinear fetches then come from LDS instead of texture units.  The
+// corners are projected by eight lanes each and reduced across lanes with DPP
+// moves, so every wave gets the footprint without an extra barrier.
 //
 // For a circular trajectory about z (AXIAL: the matrices have no z term in
 // the u and w rows) the column coordinate, the depth w and the weight are
@@ -17,8 +20,8 @@
 namespace ph {
 namespace {
 
-constexpr int BP_TW = 64;  // max staged footprint width (detector columns)
-constexpr int BP_TH = 64;  // max staged footprint height (detector rows)
+constexpr int BP_TW = 64;    // max staged footprint width (detector columns)
+constexpr int BP_TH = 128;   // max staged footprint height (detector rows)
 
 template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
@@ -31,46 +34,99 @@ __device__ __forceinline__ float dot4(const float r[4], float x, float y, float 
     return fmaf(r[0], x, fmaf(r[1], y, fmaf(r[2], z, r[3])));
 }
 
-template <typename T, typename TI, int NZ, bool AXIAL>
+// 1/x from the hardware estimate refined by one Newton step
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// min / max over the 8 lanes of each group {l : l mod 8 fixed... } holding
+// the 8 corners: xor 1 and xor 2 within quads, then rotate a row by 4 lanes
+// (pairs a quad of corners 0-3 with one of corners 4-7).
+__device__ __forceinline__ float min8(float x)
+{
+    x = fminf(x, dpp<0xB1>(x));
+    x = fminf(x, dpp<0x4E>(x));
+    return fminf(x, dpp<0x124>(x));
+}
+__device__ __forceinline__ float max8(float x)
+{
+    x = fmaxf(x, dpp<0xB1>(x));
+    x = fmaxf(x, dpp<0x4E>(x));
+    return fmaxf(x, dpp<0x124>(x));
+}
+
+// bilinear fetch at tile-local coordinates, unit-stride columns
+__device__ __forceinline__ float bilerp_tile(const float *p, float fu, float fv)
+{
+    const float p00 = p[0], p01 = p[1], p10 = p[BP_TW], p11 = p[BP_TW + 1];
+    const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
+    return fmaf(fv, a1 - a0, a0);
+}
+
+template <typename TI>
+__device__ __forceinline__ float bilerp_global(const TI *q, const Geom3D &g, float su, float sv)
+{
+    const float fsu = floorf(su), fsv = floorf(sv);
+    const int j = (int)fsu, i = (int)fsv;
+    const float fu = su - fsu, fv = sv - fsv;
+    const float p00 = det_pix(q, g.nu, g.nv, i, j), p01 = det_pix(q, g.nu, g.nv, i, j + 1);
+    const float p10 = det_pix(q, g.nu, g.nv, i + 1, j), p11 = det_pix(q, g.nu, g.nv, i + 1, j + 1);
+    const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
+    return fmaf(fv, a1 - a0, a0);
+}
+
+template <typename T, typename TI, int BP_NZ, bool AXIAL>
 __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
-                                                      const TI *__restrict__ proj, T *__restrict__ vol, int nzb)
+                                                      const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
+                                                      int nby, int nzb)
 {
     __shared__ float tile[BP_TH * BP_TW];
     const int tid = threadIdx.x;
-    const int ix = blockIdx.x * 16 + (tid & 15);
-    const int iy = blockIdx.y * 16 + (tid >> 4);
-    const int zb = blockIdx.z % nzb, b = blockIdx.z / nzb;
-    const int z0 = zb * NZ;
-    const int zcount = min(NZ, g.nz - z0);
+    const int tx = tid & 15, ty = tid >> 4;
+    // Workgroups are handed to the 8 XCDs round-robin by linear id; remap so
+    // that each XCD takes a contiguous run of bricks in z-major order, i.e. a
+    // z slab, whose detector-row band then stays in that XCD's L2.
+    const unsigned total = gridDim.x;
+    unsigned lin = blockIdx.x;
+    if (lin < total - total % 8u)
+        lin = (lin % 8u) * (total / 8u) + lin / 8u;
+    const int bxi = (int)(lin % (unsigned)nbx), byi = (int)((lin / (unsigned)nbx) % (unsigned)nby);
+    const int bzb = (int)(lin / (unsigned)(nbx * nby));
+    const int ix = bxi * 16 + tx;
+    const int iy = byi * 16 + ty;
+    const int zb = bzb % nzb, b = bzb / nzb;
+    const int z0 = zb * BP_NZ;
+    const int zcount = min(BP_NZ, g.nz - z0);
     const bool active = ix < g.nx && iy < g.ny;
 
     const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
     const float xc = (float)ix - hx, yc = (float)iy - hy, zc0 = (float)z0 - hz;
-    // brick corners (centred voxel indices), clamped to the grid
-    const float bx0 = (float)(blockIdx.x * 16) - hx, bx1 = (float)min(blockIdx.x * 16 + 15, g.nx - 1) - hx;
-    const float by0 = (float)(blockIdx.y * 16) - hy, by1 = (float)min(blockIdx.y * 16 + 15, g.ny - 1) - hy;
-    const float bz0 = zc0, bz1 = zc0 + (float)(zcount - 1);
+    // this lane's brick corner (centred voxel indices), clamped to the grid
+    const int corner = tid & 7;
+    const float cx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) : bxi * 16) - hx;
+    const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
+    const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
 
     const TI *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
-    float acc[NZ];
+    float acc[BP_NZ];
 #pragma unroll
-    for (int z = 0; z < NZ; ++z)
+    for (int z = 0; z < BP_NZ; ++z)
         acc[z] = 0.0f;
 
     for (int k = 0; k < g.n_proj; ++k) {
-        ConeBPView v = views[k];
-        // footprint of the brick: extreme detector coordinates over the corners
-        float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float cx = (c & 1) ? bx1 : bx0, cy = (c & 2) ? by1 : by0, cz = (c & 4) ? bz1 : bz0;
-            const float rw = 1.0f / dot4(v.r[2], cx, cy, cz);
-            const float uu = dot4(v.r[0], cx, cy, cz) * rw, vv = dot4(v.r[1], cx, cy, cz) * rw;
-            umin = fminf(umin, uu);
-            umax = fmaxf(umax, uu);
-            vmin = fminf(vmin, vv);
-            vmax = fmaxf(vmax, vv);
-        }
+        const ConeBPView v = views[k];
+        // footprint of the brick on the detector
+        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
+        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
+        const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
         const int u_lo = (int)floorf(umin + g.cu) - 1, u_hi = (int)floorf(umax + g.cu) + 2;
         const int v_lo = (int)floorf(vmin + g.cv) - 1, v_hi = (int)floorf(vmax + g.cv) + 2;
         const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
@@ -78,87 +134,74 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
         const TI *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged) {
             __syncthreads();
-            for (int idx = tid; idx < tw * th; idx += 256) {
-                const int r = idx / tw, c = idx - r * tw;
-                tile[r * BP_TW + c] = det_pix(qk, g.nu, g.nv, v_lo + r, u_lo + c);
+            for (int r = ty; r < th; r += 16) {
+                const int gi = v_lo + r;
+                const bool row_ok = (unsigned)gi < (unsigned)g.nv;
+                const TI *rowp = qk + (size_t)(row_ok ? gi : 0) * g.nu;
+                for (int c = tx; c < tw; c += 16) {
+                    const int gj = u_lo + c;
+                    tile[r * BP_TW + c] = (row_ok && (unsigned)gj < (unsigned)g.nu) ? load_f32(rowp + gj) : 0.0f;
+                }
             }
             __syncthreads();
         }
         if (!active)
             continue;
         if (AXIAL) {
-            const float W = dot4(v.r[2], xc, yc, zc0);
-            const float rW = 1.0f / W;
+            const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc0));
             const float sw = g.sid * rW, wt = sw * sw;
             const float uc = dot4(v.r[0], xc, yc, zc0) * rW;
             const float vc0 = dot4(v.r[1], xc, yc, zc0) * rW;
             const float dvz = v.r[1][2] * rW;
             if (staged) {
+                // tile-local coordinates are >= 1 (one-pixel margin): floor == truncation
                 const float su = uc + g.cu - (float)u_lo;
                 const float sv0 = vc0 + g.cv - (float)v_lo;
                 const int iu = (int)su;
-                const float fu = su - (float)iu;
+                const float fu = __builtin_amdgcn_fractf(su);
                 const float *col = tile + iu;
+                if (zcount == BP_NZ) {
 #pragma unroll
-                for (int z = 0; z < NZ; ++z) {
-                    if (z < zcount) {
+                    for (int z = 0; z < BP_NZ; ++z) {
                         const float sv = fmaf((float)z, dvz, sv0);
                         const int iv = (int)sv;
-                        const float fv = sv - (float)iv;
-                        const float *p = col + iv * BP_TW;
-                        const float p00 = p[0], p01 = p[1], p10 = p[BP_TW], p11 = p[BP_TW + 1];
-                        const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
-                        acc[z] = fmaf(wt, fmaf(fv, a1 - a0, a0), acc[z]);
+                        acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TW, fu, __builtin_amdgcn_fractf(sv)), acc[z]);
+                    }
+                } else {
+#pragma unroll
+                    for (int z = 0; z < BP_NZ; ++z) {
+                        if (z < zcount) {
+                            const float sv = fmaf((float)z, dvz, sv0);
+                            const int iv = (int)sv;
+                            acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TW, fu, __builtin_amdgcn_fractf(sv)),
+                                          acc[z]);
+                        }
                     }
                 }
             } else {
-                const float su = uc + g.cu;
-                const float fsu = floorf(su);
-                const int j = (int)fsu;
-                const float fu = su - fsu;
-                const float sv0 = vc0 + g.cv;
+                const float su = uc + g.cu, sv0 = vc0 + g.cv;
 #pragma unroll
-                for (int z = 0; z < NZ; ++z) {
-                    if (z < zcount) {
-                        const float sv = fmaf((float)z, dvz, sv0);
-                        const float fsv = floorf(sv);
-                        const int i = (int)fsv;
-                        const float fv = sv - fsv;
-                        const float p00 = det_pix(qk, g.nu, g.nv, i, j), p01 = det_pix(qk, g.nu, g.nv, i, j + 1);
-                        const float p10 = det_pix(qk, g.nu, g.nv, i + 1, j);
-                        const float p11 = det_pix(qk, g.nu, g.nv, i + 1, j + 1);
-                        const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
-                        acc[z] = fmaf(wt, fmaf(fv, a1 - a0, a0), acc[z]);
-                    }
-                }
+                for (int z = 0; z < BP_NZ; ++z)
+                    if (z < zcount)
+                        acc[z] = fmaf(wt, bilerp_global(qk, g, su, fmaf((float)z, dvz, sv0)), acc[z]);
             }
         } else {
 #pragma unroll
-            for (int z = 0; z < NZ; ++z) {
+            for (int z = 0; z < BP_NZ; ++z) {
                 if (z < zcount) {
                     const float zc = zc0 + (float)z;
-                    const float rW = 1.0f / dot4(v.r[2], xc, yc, zc);
+                    const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
                     const float sw = g.sid * rW, wt = sw * sw;
-                    float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
-                    float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
+                    const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
+                    const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
                     if (staged) {
-                        su -= (float)u_lo;
-                        sv -= (float)v_lo;
-                        const int iu = (int)su, iv = (int)sv;
-                        const float fu = su - (float)iu, fv = sv - (float)iv;
-                        const float *p = tile + iv * BP_TW + iu;
-                        const float p00 = p[0], p01 = p[1], p10 = p[BP_TW], p11 = p[BP_TW + 1];
-                        const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
-                        acc[z] = fmaf(wt, fmaf(fv, a1 - a0, a0), acc[z]);
+                        const float lu = su - (float)u_lo, lv = sv - (float)v_lo;
+                        const int iu = (int)lu, iv = (int)lv;
+                        acc[z] = fmaf(wt, bilerp_tile(tile + iv * BP_TW + iu, __builtin_amdgcn_fractf(lu),
+                                                      __builtin_amdgcn_fractf(lv)),
+                                      acc[z]);
                     } else {
-                        const float fsu = floorf(su), fsv = floorf(sv);
-                        const int j = (int)fsu, i = (int)fsv;
-                        const float fu = su - fsu, fv = sv - fsv;
-                        const float p00 = det_pix(qk, g.nu, g.nv, i, j), p01 = det_pix(qk, g.nu, g.nv, i, j + 1);
-                        const float p10 = det_pix(qk, g.nu, g.nv, i + 1, j);
-                        const float p11 = det_pix(qk, g.nu, g.nv, i + 1, j + 1);
-                        const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
-                        acc[z] = fmaf(wt, fmaf(fv, a1 - a0, a0), acc[z]);
+                        acc[z] = fmaf(wt, bilerp_global(qk, g, su, sv), acc[z]);
                     }
                 }
             }
@@ -168,40 +211,50 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
         return;
     T *out = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)iy * g.nx + ix;
 #pragma unroll
-    for (int z = 0; z < NZ; ++z)
+    for (int z = 0; z < BP_NZ; ++z)
         if (z < zcount)
             store_f32(out + (size_t)(z0 + z) * g.ny * g.nx, g.dbeta * acc[z]);
 }
 
-template <typename T, typename TI>
-hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, bool axial, const void *proj, void *vol, int batch,
-                   hipStream_t s)
+template <typename T, typename TI, int NZ>
+hipError_t bp_cone_nz(const Geom3D &g, const ConeBPView *views, bool axial, const void *proj, void *vol, int batch,
+                      hipStream_t s)
 {
-    constexpr int NZ = 16;
-    const int nzb = (g.nz + NZ - 1) / NZ;
-    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, nzb * batch);
+    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
+    const unsigned blocks = (unsigned)(nbx * nby * nzb * batch);
     if (axial)
-        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, true>), grid, dim3(256), 0, s, g, views, (const TI *)proj,
-                           (T *)vol, nzb);
+        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, true>), dim3(blocks), dim3(256), 0, s, g, views,
+                           (const TI *)proj, (T *)vol, nbx, nby, nzb);
     else
-        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, false>), grid, dim3(256), 0, s, g, views, (const TI *)proj,
-                           (T *)vol, nzb);
+        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, false>), dim3(blocks), dim3(256), 0, s, g, views,
+                           (const TI *)proj, (T *)vol, nbx, nby, nzb);
     return hipGetLastError();
+}
+
+template <typename T, typename TI>
+hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg, const void *proj, void *vol,
+                   int batch, hipStream_t s)
+{
+    if (nz_seg >= 64)
+        return bp_cone_nz<T, TI, 64>(g, views, axial, proj, vol, batch, s);
+    if (nz_seg >= 32)
+        return bp_cone_nz<T, TI, 32>(g, views, axial, proj, vol, batch, s);
+    return bp_cone_nz<T, TI, 16>(g, views, axial, proj, vol, batch, s);
 }
 
 }  // namespace
 
-hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial,
+hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
                                    const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream)
 {
     switch (dtype) {
-    case 0: return bp_cone<float, float>(g, views, axial, proj, vol, batch, stream);
+    case 0: return bp_cone<float, float>(g, views, axial, nz_seg, proj, vol, batch, stream);
     case 1:
-        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, axial, proj, vol, batch, stream)
-                           : bp_cone<f16_t, f16_t>(g, views, axial, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, axial, nz_seg, proj, vol, batch, stream)
+                           : bp_cone<f16_t, f16_t>(g, views, axial, nz_seg, proj, vol, batch, stream);
     default:
-        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, axial, proj, vol, batch, stream)
-                           : bp_cone<bf16_t, bf16_t>(g, views, axial, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, axial, nz_seg, proj, vol, batch, stream)
+                           : bp_cone<bf16_t, bf16_t>(g, views, axial, nz_seg, proj, vol, batch, stream);
     }
 }
 

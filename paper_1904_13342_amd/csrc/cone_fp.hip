@@ -3,10 +3,28 @@
 // ray from the source through the pixel is sampled at fixed steps on the
 // lattice anchored at its point closest to the isocentre, and the volume is
 // interpolated trilinearly with zero outside the grid.
+//
+// Mapping: a workgroup owns a 16 x 16 detector tile of one view.  Its rays
+// form a thin pyramid from the source, and all of them travel mostly along one
+// horizontal axis A (x or y, the larger component of the view's central ray).
+// The volume is walked in slabs of D planes across A; for each slab the
+// cross-section of the pyramid (bounded by the tile's four corner rays, plus a
+// one-voxel margin, clipped to the grid and a two-voxel zero halo) is staged
+// in LDS, and every ray then takes the samples whose floor(A coordinate)
+// falls in the slab, with all eight trilinear corners read from LDS.  A sample
+// belongs to exactly one slab, decided by the same FP32 coordinate the
+// interpolation uses.  Slabs that do not fit in LDS, and tiles whose rays do
+// not share a dominant axis, read the volume directly.
 #include "common.h"
 
 namespace ph {
 namespace {
+
+constexpr int FP_TILE = 16;            // detector tile edge (pixels)
+constexpr int FP_D = 8;                // slab depth (planes along A)
+constexpr int FP_WA = FP_D + 1;        // planes held per slab
+constexpr int FP_LDS_FLOATS = 10240;   // 40 KiB slab capacity
+constexpr int FP_BIAS = 4;             // keeps biased coordinates positive (floor == truncation)
 
 template <typename T>
 __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix, int iy, int iz)
@@ -26,18 +44,17 @@ __device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float
     return true;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView *__restrict__ views,
-                                                      const T *__restrict__ vol, T *__restrict__ proj)
+// Index coordinates (x, y, z) of a ray's anchor (its point closest to the
+// isocentre) and of one sampling step.
+struct Ray {
+    float p[3], e[3];
+};
+
+// Ray of detector pixel (j, i), set up in double precision (the source is
+// ~SID away, so an FP32 direction would misplace the ray by ~SID * 2^-24 at
+// the volume) and rounded once to FP32.
+__device__ __forceinline__ Ray make_ray(const Geom3D &g, const ConeFPView &v, int j, int i)
 {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int k = blockIdx.z % g.n_proj, b = blockIdx.z / g.n_proj;
-    if (j >= g.nu || i >= g.nv)
-        return;
-    // ray setup in double precision: anchor (point closest to the isocentre)
-    // and unit direction, then index coordinates rounded once to FP32
-    const ConeFPView &v = views[k];
     const double jc = (double)j - (double)g.cu, ic = (double)i - (double)g.cv;
     double d[3];
 #pragma unroll
@@ -48,43 +65,241 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     for (int t = 0; t < 3; ++t)
         d[t] *= rn;
     const double t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
-    const float X0 = (float)((fma(t0, d[0], v.s[0]) - (double)g.ox) / (double)g.sx);
-    const float Y0 = (float)((fma(t0, d[1], v.s[1]) - (double)g.oy) / (double)g.sy);
-    const float Z0 = (float)((fma(t0, d[2], v.s[2]) - (double)g.oz) / (double)g.sz);
-    const float eX = (float)((double)g.step * d[0] / (double)g.sx);
-    const float eY = (float)((double)g.step * d[1] / (double)g.sy);
-    const float eZ = (float)((double)g.step * d[2] / (double)g.sz);
-    float lo = -3.0e38f, hi = 3.0e38f;
-    float acc = 0.0f;
-    const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;
-    if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && krange(Z0, eZ, g.nz, lo, hi) && lo < hi) {
-        const int k0 = (int)floorf(lo) - 1, k1 = (int)ceilf(hi) + 1;
-        for (int m = k0; m <= k1; ++m) {
-            const float fm = (float)m;
-            const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0), Z = fmaf(fm, eZ, Z0);
-            const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
-            const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-            const float tx = X - fx, ty = Y - fy, tz = Z - fz;
-            float c[2];
+    const double o[3] = {g.ox, g.oy, g.oz}, s[3] = {g.sx, g.sy, g.sz};
+    Ray r;
 #pragma unroll
-            for (int dz = 0; dz < 2; ++dz) {
-                const float p00 = vox(f, g.nx, g.ny, g.nz, ix, iy, iz + dz);
-                const float p01 = vox(f, g.nx, g.ny, g.nz, ix + 1, iy, iz + dz);
-                const float p10 = vox(f, g.nx, g.ny, g.nz, ix, iy + 1, iz + dz);
-                const float p11 = vox(f, g.nx, g.ny, g.nz, ix + 1, iy + 1, iz + dz);
-                const float a0 = fmaf(tx, p01 - p00, p00), a1 = fmaf(tx, p11 - p10, p10);
-                c[dz] = fmaf(ty, a1 - a0, a0);
+    for (int t = 0; t < 3; ++t) {
+        r.p[t] = (float)((fma(t0, d[t], v.s[t]) - o[t]) / s[t]);
+        r.e[t] = (float)((double)g.step * d[t] / s[t]);
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ float sample_global(const T *f, const Geom3D &g, float X, float Y, float Z)
+{
+    const float fx = floorf(X), fy = floorf(Y), fz = floorf(Z);
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const float tx = X - fx, ty = Y - fy, tz = Z - fz;
+    float c[2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const float p00 = vox(f, g.nx, g.ny, g.nz, ix, iy, iz + dz);
+        const float p01 = vox(f, g.nx, g.ny, g.nz, ix + 1, iy, iz + dz);
+        const float p10 = vox(f, g.nx, g.ny, g.nz, ix, iy + 1, iz + dz);
+        const float p11 = vox(f, g.nx, g.ny, g.nz, ix + 1, iy + 1, iz + dz);
+        const float a0 = fmaf(tx, p01 - p00, p00), a1 = fmaf(tx, p11 - p10, p10);
+        c[dz] = fmaf(ty, a1 - a0, a0);
+    }
+    return fmaf(tz, c[1] - c[0], c[0]);
+}
+
+// Whether sample m (biased A coordinate fma(m, eA, PA0)) lies in the slab
+// whose first biased plane is offA.
+__device__ __forceinline__ bool in_slab(int m, float eA, float PA0, int offA)
+{
+    return (unsigned)((int)fmaf((float)m, eA, PA0) - offA) < (unsigned)FP_D;
+}
+
+// Trilinear sample m from the LDS slab ([c][b][a], a fastest; biased
+// coordinates are positive, so truncation is floor).
+__device__ __forceinline__ float sample_lds(const float *slab, int m, float PA0, float eA, float PB0, float eB,
+                                            float PC0, float eC, int HB, int base, int sb, int sc)
+{
+    const float fm = (float)m;
+    const float A = fmaf(fm, eA, PA0), B = fmaf(fm, eB, PB0), C = fmaf(fm, eC, PC0);
+    const int iA = (int)A, iB = (int)B, iC = (int)C;
+    const float tA = __builtin_amdgcn_fractf(A), tB = __builtin_amdgcn_fractf(B), tC = __builtin_amdgcn_fractf(C);
+    const int cell = __mul24(__mul24(iC, HB) + iB, FP_WA) + iA + base;
+    const float *p = slab + cell;
+    const float l00 = fmaf(tA, p[1] - p[0], p[0]);
+    const float l10 = fmaf(tA, p[sb + 1] - p[sb], p[sb]);
+    const float l01 = fmaf(tA, p[sc + 1] - p[sc], p[sc]);
+    const float l11 = fmaf(tA, p[sc + sb + 1] - p[sc + sb], p[sc + sb]);
+    const float m0 = fmaf(tB, l10 - l00, l00), m1 = fmaf(tB, l11 - l01, l01);
+    return fmaf(tC, m1 - m0, m0);
+}
+
+// Slab walk of one tile along the dominant axis AX (0: x, 1: y); B is the
+// other horizontal axis, C = z.  LDS layout [c][b][a], a fastest.
+template <typename T, int AX>
+__device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *slab, int *s_range, const Ray &r,
+                                           const Ray cr[4], bool hit, int kb, int ke)
+{
+    constexpr int BX = 1 - AX;
+    const int tid = threadIdx.x;
+    const int NB = AX == 0 ? g.ny : g.nx, NC = g.nz;
+    const float sgn = cr[0].e[AX] > 0.0f ? 1.0f : -1.0f;
+    // biased coordinates of this ray
+    const float PA0 = r.p[AX] + (float)FP_BIAS, eA = r.e[AX];
+    const float PB0 = r.p[BX] + (float)FP_BIAS, eB = r.e[BX];
+    const float PC0 = r.p[2] + (float)FP_BIAS, eC = r.e[2];
+
+    // slabs cover floor(A) in [-2, NA]; slab s holds floor(A) in [-2 + s D, -2 + (s+1) D)
+    if (tid == 0) {
+        s_range[0] = 1 << 30;
+        s_range[1] = -(1 << 30);
+    }
+    __syncthreads();
+    if (hit) {
+        const int ia = (int)fmaf((float)kb, eA, PA0) - FP_BIAS, ie = (int)fmaf((float)ke, eA, PA0) - FP_BIAS;
+        atomicMin(&s_range[0], (min(ia, ie) + 2) / FP_D);
+        atomicMax(&s_range[1], (max(ia, ie) + 2) / FP_D);
+    }
+    __syncthreads();
+    const int s_min = s_range[0], s_max = s_range[1];
+
+    float acc = 0.0f;
+    int m = kb;   // next sample of this ray
+    for (int n = 0; n <= s_max - s_min; ++n) {
+        const int s = sgn > 0.0f ? s_min + n : s_max - n;
+        const int a0 = -2 + s * FP_D;   // first plane of the slab
+        // cross-section of the tile's pyramid between planes a0 and a0 + D
+        float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const float t = ((float)(a0 + e * FP_D) - cr[c].p[AX]) / cr[c].e[AX];
+                const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
+                bmin = fminf(bmin, bb);
+                bmax = fmaxf(bmax, bb);
+                cmin = fminf(cmin, cc);
+                cmax = fmaxf(cmax, cc);
             }
-            acc += fmaf(tz, c[1] - c[0], c[0]);
+        }
+        const int b_lo = max((int)floorf(bmin) - 1, -2), b_hi = min((int)floorf(bmax) + 2, NB + 1);
+        const int c_lo = max((int)floorf(cmin) - 1, -2), c_hi = min((int)floorf(cmax) + 2, NC + 1);
+        const int HB = b_hi - b_lo + 1, HC = c_hi - c_lo + 1;
+        const bool staged = HB > 0 && HC > 0 && FP_WA * HB * HC <= FP_LDS_FLOATS;
+        if (staged) {
+            __syncthreads();   // the previous slab has been consumed
+            // each thread owns fixed (a, b) cells of the slab and walks them up
+            // through the z planes; rows along x (the fastest axis in memory)
+            // keep the loads coalesced
+            const int L = AX == 0 ? FP_WA : HB;   // x-run length
+            const int plane = FP_WA * HB;         // cells per z plane
+            const float invL = 1.0f / (float)L;
+            for (int q = tid; q < plane; q += 256) {
+                int row = (int)(((float)q + 0.5f) * invL);   // quotient, corrected to exact
+                int col = q - row * L;
+                row += (col >= L) - (col < 0);
+                col = q - row * L;
+                const int ia = AX == 0 ? col : row, ib = AX == 0 ? row : col;
+                const int ga = a0 + ia, gb = b_lo + ib;
+                const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
+                const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
+                const T *src = f + (size_t)(in_xy ? gy : 0) * g.nx + (in_xy ? gx : 0);
+                float *dst = slab + ib * FP_WA + ia;
+                const size_t zstride = (size_t)g.nx * g.ny;
+                for (int ic = 0; ic < HC; ++ic) {
+                    const int gz = c_lo + ic;
+                    dst[ic * plane] = (in_xy && (unsigned)gz < (unsigned)g.nz) ? load_f32(src + (size_t)gz * zstride)
+                                                                                : 0.0f;
+                }
+            }
+            __syncthreads();
+        }
+        if (!hit)
+            continue;
+        // samples of this ray inside the slab: m .. m_end-1, counted exactly
+        // with the FP32 coordinate the interpolation uses (A is monotonic in m)
+        const int offA = a0 + FP_BIAS, offB = b_lo + FP_BIAS, offC = c_lo + FP_BIAS;
+        int m_end = m;
+        if (m <= ke && in_slab(m, eA, PA0, offA)) {
+            const float bound = sgn > 0.0f ? (float)(offA + FP_D) : (float)offA;
+            const float est = (bound - fmaf((float)m, eA, PA0)) / eA;
+            m_end = min(m + max((int)ceilf(est), 1), ke + 1);
+            while (m_end > m + 1 && !in_slab(m_end - 1, eA, PA0, offA))
+                --m_end;
+            while (m_end <= ke && in_slab(m_end, eA, PA0, offA))
+                ++m_end;
+        }
+        if (staged) {
+            // LDS cell of biased coordinates (A, B, C), as a dword index
+            const int base = -(offC * HB + offB) * FP_WA - offA;
+            const int sb = FP_WA, sc = FP_WA * HB;
+            for (; m + 1 < m_end; m += 2) {
+                acc += sample_lds(slab, m, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
+                acc += sample_lds(slab, m + 1, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
+            }
+            if (m < m_end) {
+                acc += sample_lds(slab, m, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
+                ++m;
+            }
+        } else {
+            for (; m < m_end; ++m) {
+                const float fm = (float)m;
+                float q[3];
+                q[AX] = fmaf(fm, eA, PA0) - (float)FP_BIAS;
+                q[BX] = fmaf(fm, eB, PB0) - (float)FP_BIAS;
+                q[2] = fmaf(fm, eC, PC0) - (float)FP_BIAS;
+                acc += sample_global(f, g, q[0], q[1], q[2]);
+            }
         }
     }
-    store_f32(proj + (((size_t)b * g.n_proj + k) * g.nv + i) * g.nu + j, g.step * acc);
+    return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView *__restrict__ views,
+                                                      const T *__restrict__ vol, T *__restrict__ proj)
+{
+    __shared__ float slab[FP_LDS_FLOATS];
+    __shared__ int s_range[2];
+    const int tid = threadIdx.x;
+    const int j0 = blockIdx.x * FP_TILE, i0 = blockIdx.y * FP_TILE;
+    const int j = j0 + (tid % FP_TILE), i = i0 + (tid / FP_TILE);
+    const int k = blockIdx.z % g.n_proj, b = blockIdx.z / g.n_proj;
+    const bool valid = j < g.nu && i < g.nv;
+    const ConeFPView &v = views[k];
+    const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;
+
+    const Ray r = make_ray(g, v, valid ? j : j0, valid ? i : i0);
+    float lo = -3.0e38f, hi = 3.0e38f;
+    const bool hit = valid && krange(r.p[0], r.e[0], g.nx, lo, hi) && krange(r.p[1], r.e[1], g.ny, lo, hi) &&
+                     krange(r.p[2], r.e[2], g.nz, lo, hi) && lo < hi;
+    // one sample of margin on each side; samples outside the box add zeros
+    const int kb = hit ? (int)floorf(lo) : 0, ke = hit ? (int)ceilf(hi) : -1;
+
+    // the tile's four corner rays bound the pyramid of its rays
+    const int jh = min(j0 + FP_TILE - 1, g.nu - 1), ih = min(i0 + FP_TILE - 1, g.nv - 1);
+    Ray cr[4];
+    cr[0] = make_ray(g, v, j0, i0);
+    cr[1] = make_ray(g, v, jh, i0);
+    cr[2] = make_ray(g, v, j0, ih);
+    cr[3] = make_ray(g, v, jh, ih);
+    const int ax = fabs(v.d0[0]) >= fabs(v.d0[1]) ? 0 : 1;
+    // every ray must advance along A in one direction, at least as fast as
+    // across it, and by at most one voxel per step (margin samples stay
+    // inside the two-voxel halo)
+    bool slab_ok = g.step <= fminf(g.sx, fminf(g.sy, g.sz));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float eA = cr[c].e[ax], eB = cr[c].e[1 - ax];
+        slab_ok = slab_ok && eA * cr[0].e[ax] > 0.0f && fabsf(eA) >= fabsf(eB) && fabsf(eA) >= fabsf(cr[c].e[2]) &&
+                  fabsf(eA) <= 1.0f && fabsf(eB) <= 1.0f && fabsf(cr[c].e[2]) <= 1.0f;
+    }
+
+    float acc = 0.0f;
+    if (!slab_ok) {
+        for (int m = kb; m <= ke; ++m) {
+            const float fm = (float)m;
+            acc += sample_global(f, g, fmaf(fm, r.e[0], r.p[0]), fmaf(fm, r.e[1], r.p[1]), fmaf(fm, r.e[2], r.p[2]));
+        }
+    } else if (ax == 0) {
+        acc = slab_walk<T, 0>(g, f, slab, s_range, r, cr, hit, kb, ke);
+    } else {
+        acc = slab_walk<T, 1>(g, f, slab, s_range, r, cr, hit, kb, ke);
+    }
+    if (valid)
+        store_f32(proj + (((size_t)b * g.n_proj + k) * g.nv + i) * g.nu + j, g.step * acc);
 }
 
 template <typename T>
 hipError_t fp_cone(const Geom3D &g, const ConeFPView *views, const void *vol, void *proj, int batch, hipStream_t s)
 {
-    dim3 grid((g.nu + 63) / 64, (g.nv + 3) / 4, g.n_proj * batch);
+    dim3 grid((g.nu + FP_TILE - 1) / FP_TILE, (g.nv + FP_TILE - 1) / FP_TILE, g.n_proj * batch);
     hipLaunchKernelGGL((fp_cone_kernel<T>), grid, dim3(256), 0, s, g, views, (const T *)vol, (T *)proj);
     return hipGetLastError();
 }
