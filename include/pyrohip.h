@@ -136,6 +136,36 @@ int ph_backproject_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *
 int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
                           int dtype, void *stream);
 
+/* ------------------------------------------------- exact transposes
+ * Sec. II.B.2: the ray-driven projector and the voxel-driven back-projector
+ * are an unmatched pair; Sec. II.B.1 (after Eq. 4) uses each operator's
+ * adjoint for the gradient.  These are the exact transposes of the two
+ * operators above, for matched gradients.
+ *
+ * ph_project_adjoint_*: A^T, volume_x = step * sum_r g_r sum_k Lambda(X_rk - x)
+ * over the same sample positions X_rk as ph_project_* (Lambda the bi/trilinear
+ * hat function).  Gather, no atomics; any storage dtype.
+ *   sino/proj : device input, same layout as the projector's output
+ *   img/vol   : device output, same layout as the projector's input
+ * ph_backproject_adjoint_*: B^T, projection_(k,i,j) = dbeta * sum_x f(x)
+ * w_k(x) Lambda(j - su_k(x)) Lambda(i - sv_k(x)) with w_k = 1 (parallel) or
+ * (SID/w)^2.  Scatter with float atomics: FP32 storage only (other dtypes ->
+ * PH_ERR_UNSUPPORTED); summation order, hence the last bits, may vary from
+ * run to run.
+ *   img/vol   : device FP32 input; sino/proj : device FP32 output */
+int ph_project_adjoint_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
+                             int dtype, void *stream);
+int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
+                             int dtype, void *stream);
+int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
+                              int dtype, void *stream);
+int ph_backproject_adjoint_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
+                                 int dtype, void *stream);
+int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
+                                 int dtype, void *stream);
+int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
+                                  int dtype, void *stream);
+
 /* --------------------------------------------- weighting + ramp filtering
  * Eq. 4 / Eq. 5 without the back-projection: q = F^H K F (W_red * W_cos * W * p),
  * row by row (detector rows along u).  Sec. II.C.4 (Ramp / Ram-Lak filters as
@@ -145,7 +175,7 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
  *           Ram-Lak with sample spacing tau (du for parallel, du*SID/SDD for
  *           fan/cone) and M = smallest power of two >= 2*nu-1 (then the row
  *           filter is an exact linear convolution);  M must be a power of two
- *           in [max(16, nu), 8192];  with K given the output is
+ *           in [max(16, nu), 4096];  with K given the output is
  *           Re IDFT_M(K . DFT_M(zero-padded row)), first nu samples;
  *   W_red : device float[n_proj][nu] or NULL -> parallel: pi/range;
  *           fan/cone: 1/2 for a full turn, Parker for a short scan;

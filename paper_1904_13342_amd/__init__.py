@@ -9,4 +9,7 @@ from ._lib import lib as _load_lib
 _load_lib()
 
 from .ops import *  # noqa: E402,F401,F403
-from .ops import __all__  # noqa: E402,F401
+from .ops import __all__ as _ops_all  # noqa: E402
+from . import autograd  # noqa: E402,F401
+
+__all__ = list(_ops_all) + ["autograd"]

@@ -64,6 +64,12 @@ SIGNATURES = {
     "ph_backproject_par2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
     "ph_backproject_fan2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
     "ph_backproject_cone3d": (_I, [_G3, _FP, _P, _P, _I, _I, _P]),
+    "ph_project_adjoint_par2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
+    "ph_project_adjoint_fan2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
+    "ph_project_adjoint_cone3d": (_I, [_G3, _FP, _P, _P, _I, _I, _P]),
+    "ph_backproject_adjoint_par2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
+    "ph_backproject_adjoint_fan2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
+    "ph_backproject_adjoint_cone3d": (_I, [_G3, _FP, _P, _P, _I, _I, _P]),
     "ph_weight_filter_2d": (_I, [_G2, _I, _P, _P, _P, _I, _P, _I, _I, _P]),
     "ph_weight_filter_3d": (_I, [_G3, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "ph_workspace_bytes_2d": (_SZ, [_G2, _I]),

@@ -260,7 +260,7 @@ void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
     }
 }
 
-// Deepest column segment (64, 32 or 16 voxels) whose 16 x 16 x NZ brick
+// Deeper column segment (32 or 16 voxels) whose 16 x 16 x NZ brick
 // footprint fits the back-projector's 64 x 128 pixel LDS tile, from a bound on
 // the magnification (nearest approach of a voxel to the source) and on the
 // row slope across a brick at the top and bottom of the volume.
@@ -278,7 +278,7 @@ int bp_segment(const ph_geom3d *g)
     const double brick = 16.0 * std::sqrt(2.0) * std::fmax(sx, sy);
     const double tw = brick * mag / g->det_spacing[1] + 4.0;
     const double slope = zmax * g->sdd / g->det_spacing[0] * brick / (wmin * wmin);
-    for (int nz = 64; nz >= 32; nz /= 2) {
+    for (int nz = 32; nz >= 32; nz /= 2) {
         const double th = nz * sz * mag / g->det_spacing[0] + slope + 4.0;
         if (tw <= 64.0 && th <= 128.0)
             return nz;
@@ -649,6 +649,29 @@ int fbp2d(const ph_geom2d *g, bool fan, const float *rv, const void *sino, void 
     return to_status(launch_backproject_2d(dtype, fan, G, views, q, true, img, batch, (hipStream_t)stream));
 }
 
+int adjoint2d(const ph_geom2d *g, bool fan, bool of_projector, const float *rv, const void *in, void *out,
+              int batch, int dtype, void *stream)
+{
+    if (!in || !out)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    if (!of_projector && dtype != PH_F32)
+        return PH_ERR_UNSUPPORTED;
+    Geom2D G;
+    const float2 *views = nullptr;
+    st = prep2d(g, fan, rv, &G, &views);
+    if (st != PH_OK)
+        return st;
+    if (of_projector)
+        return to_status(launch_project_adjoint_2d(dtype, fan, G, views, in, out, batch, (hipStream_t)stream));
+    return to_status(
+        launch_backproject_adjoint_2d(fan, G, views, (const float *)in, (float *)out, batch, (hipStream_t)stream));
+}
+
 }  // namespace
 
 extern "C" {
@@ -874,6 +897,79 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
         return st;
     return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), q, true, vol,
                                              batch, (hipStream_t)stream));
+}
+
+int ph_project_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+                             void *stream)
+{
+    return adjoint2d(g, false, true, rv, sino, img, batch, dtype, stream);
+}
+
+int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+                             void *stream)
+{
+    return adjoint2d(g, true, true, rv, sino, img, batch, dtype, stream);
+}
+
+int ph_backproject_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
+                                 int dtype, void *stream)
+{
+    return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream);
+}
+
+int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
+                                 int dtype, void *stream)
+{
+    return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream);
+}
+
+int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
+                              int dtype, void *stream)
+{
+    if (!proj || !vol)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    std::vector<double> P;
+    st = validate3d(g, mats, &G, &P);
+    if (st != PH_OK)
+        return st;
+    const void *fv = nullptr, *bv = nullptr;
+    bool axial = false;
+    st = upload3d(g, mats, P, false, &fv, &axial);
+    if (st != PH_OK)
+        return st;
+    st = upload3d(g, mats, P, true, &bv, &axial);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_project_adjoint_cone(dtype, G, (const ConeFPView *)fv, (const ConeBPView *)bv, proj, vol,
+                                                 batch, (hipStream_t)stream));
+}
+
+int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
+                                  int dtype, void *stream)
+{
+    if (!proj || !vol)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    if (dtype != PH_F32)
+        return PH_ERR_UNSUPPORTED;
+    Geom3D G;
+    const void *views = nullptr;
+    bool axial = false;
+    st = prep3d(g, mats, true, &G, &views, &axial);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_backproject_adjoint_cone(G, (const ConeBPView *)views, axial, (const float *)vol,
+                                                     (float *)proj, batch, (hipStream_t)stream));
 }
 
 }  // extern "C"

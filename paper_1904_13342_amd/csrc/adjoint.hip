@@ -1,0 +1,432 @@
+// Exact transposes of the two operators (Sec. II.B.2 notes that the
+// ray-driven projector and the voxel-driven back-projector are an unmatched
+// pair; Eq. 4 and Sec. II.B.1 use A^T as A's gradient operator).
+//
+// A^T, the transpose of the fixed-step multilinear ray sampler, is computed
+// by gather and without atomics: voxel j receives
+//     step * sum_r g_r * sum_k Lambda(X_rk - j),
+// Lambda the tensor-product hat function, X_rk the same FP32 sample positions
+// the forward projector uses.  A thread owns a voxel (2D) or a column segment
+// (3D) and walks, per view, the rays that cross its support (j - 1, j + 1)^d.
+// In 3D the rays crossing a brick's support are set up once per view into an
+// LDS table shared by the block, and every thread accumulates its segment in
+// its own LDS slots.
+//
+// B^T, the transpose of the voxel-driven distance-weighted back-projector,
+// scatters each voxel's value times dbeta * weight into the four detector
+// pixels of its bilinear footprint: in 3D into an LDS tile of the brick's
+// footprint (LDS atomics), then one global float atomic per touched pixel;
+// in 2D straight into the sinogram.  Its output is FP32.
+#include "device_util.h"
+
+namespace ph {
+namespace {
+
+// --------------------------------------------------------------- A^T, 2D
+
+template <typename T, typename TI, bool FAN>
+__global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__restrict__ views,
+                                                    const TI *__restrict__ sino, T *__restrict__ img)
+{
+    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int b = blockIdx.z;
+    if (ix >= g.nx || iy >= g.ny)
+        return;
+    const TI *sb = sino + (size_t)b * g.n_proj * g.nu;
+    const float fx = (float)ix, fy = (float)iy;
+    // corners of the support square (ix +- 1, iy +- 1) in world mm
+    const float x0 = fmaf(fx - 1.0f, g.sx, g.ox), x1 = fmaf(fx + 1.0f, g.sx, g.ox);
+    const float y0 = fmaf(fy - 1.0f, g.sy, g.oy), y1 = fmaf(fy + 1.0f, g.sy, g.oy);
+    float acc = 0.0f;
+    for (int k = 0; k < g.n_proj; ++k) {
+        const float2 c = views[k];
+        // detector bins whose rays can cross the support: project its corners
+        float smin = 3.0e38f, smax = -3.0e38f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x = (q & 1) ? x1 : x0, y = (q & 2) ? y1 : y0;
+            const float xu = -x * c.y + y * c.x;
+            const float su = FAN ? g.sdd * xu / fmaf(x, c.x, fmaf(y, c.y, g.sid)) : xu;
+            smin = fminf(smin, su);
+            smax = fmaxf(smax, su);
+        }
+        const int j0 = max((int)floorf(smin / g.du + g.cu) - 1, 0);
+        const int j1 = min((int)floorf(smax / g.du + g.cu) + 2, g.nu - 1);
+        for (int j = j0; j <= j1; ++j) {
+            const float gv = load_f32(sb + (size_t)k * g.nu + j);
+            if (gv == 0.0f)
+                continue;
+            float X0, Y0, eX, eY;
+            make_ray_2d<FAN>(g, c, j, X0, Y0, eX, eY);
+            float lo = -3.0e38f, hi = 3.0e38f;
+            if (!clip_line(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) || !clip_line(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) ||
+                !(lo < hi))
+                continue;
+            float w = 0.0f;
+            for (int m = (int)floorf(lo); m <= (int)ceilf(hi); ++m) {
+                const float X = fmaf((float)m, eX, X0), Y = fmaf((float)m, eY, Y0);
+                const float wx = 1.0f - fabsf(X - fx), wy = 1.0f - fabsf(Y - fy);
+                if (wx > 0.0f && wy > 0.0f)
+                    w = fmaf(wx, wy, w);
+            }
+            acc = fmaf(gv, w, acc);
+        }
+    }
+    store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.step * acc);
+}
+
+// --------------------------------------------------------------- A^T, 3D
+
+constexpr int AT_NZ = 8;          // voxels per column segment
+constexpr int AT_RAYS = 1024;     // rays per view held in the block's LDS table
+
+template <typename T, typename TI>
+__global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPView *__restrict__ fviews,
+                                                       const ConeBPView *__restrict__ bviews,
+                                                       const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
+                                                       int nby, int nzb)
+{
+    __shared__ float rtab[7][AT_RAYS];        // X0 Y0 Z0 eX eY eZ, step * g
+    __shared__ float accl[AT_NZ][256];        // per-thread segment accumulators
+    const int tid = threadIdx.x;
+    const int bxi = (int)(blockIdx.x % (unsigned)nbx), byi = (int)((blockIdx.x / (unsigned)nbx) % (unsigned)nby);
+    const int bzb = (int)(blockIdx.x / (unsigned)(nbx * nby));
+    const int zb = bzb % nzb, b = bzb / nzb;
+    const int ix = bxi * 16 + (tid & 15), iy = byi * 16 + (tid >> 4);
+    const int z0 = zb * AT_NZ;
+    const bool active = ix < g.nx && iy < g.ny;
+    const float fx = (float)ix, fy = (float)iy;
+#pragma unroll
+    for (int z = 0; z < AT_NZ; ++z)
+        accl[z][tid] = 0.0f;
+
+    const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
+    // support boxes in centred voxel indices: the brick's (for the table) and
+    // this column segment's (for its own loop)
+    const int corner = tid & 7;
+    const float bcx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) + 1 : bxi * 16 - 1) - hx;
+    const float bcy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) + 1 : byi * 16 - 1) - hy;
+    const float bcz = (float)((corner & 4) ? min(z0 + AT_NZ - 1, g.nz - 1) + 1 : z0 - 1) - hz;
+    const TI *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
+
+    for (int k = 0; k < g.n_proj; ++k) {
+        const ConeBPView bv = bviews[k];
+        const ConeFPView &fv = fviews[k];
+        const float rw = rcp_nr(dot4(bv.r[2], bcx, bcy, bcz));
+        const float cu = dot4(bv.r[0], bcx, bcy, bcz) * rw, cv = dot4(bv.r[1], bcx, bcy, bcz) * rw;
+        const int j_lo = max((int)floorf(min8(cu) + g.cu) - 1, 0), j_hi = min((int)floorf(max8(cu) + g.cu) + 2, g.nu - 1);
+        const int i_lo = max((int)floorf(min8(cv) + g.cv) - 1, 0), i_hi = min((int)floorf(max8(cv) + g.cv) + 2, g.nv - 1);
+        const int W = j_hi - j_lo + 1, H = i_hi - i_lo + 1;
+        const bool staged = W > 0 && H > 0 && W * H <= AT_RAYS;
+        const TI *qk = pb + (size_t)k * g.nv * g.nu;
+        __syncthreads();   // the previous view's table has been consumed
+        if (staged) {
+            for (int idx = tid; idx < W * H; idx += 256) {
+                const int ii = idx / W, jj = idx - ii * W;
+                const Ray r = make_cone_ray(g, fv, j_lo + jj, i_lo + ii);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    rtab[t][idx] = r.p[t];
+                    rtab[3 + t][idx] = r.e[t];
+                }
+                rtab[6][idx] = g.step * load_f32(qk + (size_t)(i_lo + ii) * g.nu + (j_lo + jj));
+            }
+        }
+        __syncthreads();
+        if (!active || W <= 0 || H <= 0)
+            continue;
+        // rays crossing this column's support: project its 8 corners
+        float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float cx = fx + ((c & 1) ? 1.0f : -1.0f) - hx, cy = fy + ((c & 2) ? 1.0f : -1.0f) - hy;
+            const float cz = (float)((c & 4) ? min(z0 + AT_NZ - 1, g.nz - 1) + 1 : z0 - 1) - hz;
+            const float w = rcp_nr(dot4(bv.r[2], cx, cy, cz));
+            const float uu = dot4(bv.r[0], cx, cy, cz) * w, vv = dot4(bv.r[1], cx, cy, cz) * w;
+            umin = fminf(umin, uu);
+            umax = fmaxf(umax, uu);
+            vmin = fminf(vmin, vv);
+            vmax = fmaxf(vmax, vv);
+        }
+        const int ja = max((int)floorf(umin + g.cu) - 1, j_lo), jb = min((int)floorf(umax + g.cu) + 2, j_hi);
+        const int ia = max((int)floorf(vmin + g.cv) - 1, i_lo), ib = min((int)floorf(vmax + g.cv) + 2, i_hi);
+        const float zlo = (float)(z0 - 1), zhi = (float)min(z0 + AT_NZ, g.nz);
+        for (int ii = ia; ii <= ib; ++ii) {
+            for (int jj = ja; jj <= jb; ++jj) {
+                float X0, Y0, Z0, eX, eY, eZ, gv;
+                if (staged) {
+                    const int idx = (ii - i_lo) * W + (jj - j_lo);
+                    X0 = rtab[0][idx];
+                    Y0 = rtab[1][idx];
+                    Z0 = rtab[2][idx];
+                    eX = rtab[3][idx];
+                    eY = rtab[4][idx];
+                    eZ = rtab[5][idx];
+                    gv = rtab[6][idx];
+                } else {
+                    const Ray r = make_cone_ray(g, fv, jj, ii);
+                    X0 = r.p[0];
+                    Y0 = r.p[1];
+                    Z0 = r.p[2];
+                    eX = r.e[0];
+                    eY = r.e[1];
+                    eZ = r.e[2];
+                    gv = g.step * load_f32(qk + (size_t)ii * g.nu + jj);
+                }
+                if (gv == 0.0f)
+                    continue;
+                float lo = -3.0e38f, hi = 3.0e38f;
+                if (!clip_line(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) || !clip_line(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) ||
+                    !clip_line(Z0, eZ, zlo, zhi, lo, hi) || !(lo < hi))
+                    continue;
+                for (int m = (int)floorf(lo); m <= (int)ceilf(hi); ++m) {
+                    const float fm = (float)m;
+                    const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0), Z = fmaf(fm, eZ, Z0);
+                    const float w = gv * (1.0f - fabsf(X - fx)) * (1.0f - fabsf(Y - fy));
+                    if (!(fabsf(X - fx) < 1.0f && fabsf(Y - fy) < 1.0f))
+                        continue;
+                    const float fz = floorf(Z);
+                    const float tz = Z - fz;
+                    const int iz = (int)fz - z0;
+                    if (iz >= 0 && iz < AT_NZ)
+                        accl[iz][tid] = fmaf(w, 1.0f - tz, accl[iz][tid]);
+                    if (iz + 1 >= 0 && iz + 1 < AT_NZ)
+                        accl[iz + 1][tid] = fmaf(w, tz, accl[iz + 1][tid]);
+                }
+            }
+        }
+    }
+    if (!active)
+        return;
+    T *out = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)iy * g.nx + ix;
+    for (int z = 0; z < AT_NZ && z0 + z < g.nz; ++z)
+        store_f32(out + (size_t)(z0 + z) * g.ny * g.nx, accl[z][tid]);
+}
+
+// --------------------------------------------------------------- B^T, 2D
+
+__global__ void fill_zero_kernel(float *__restrict__ p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+template <typename TI, bool FAN>
+__global__ void __launch_bounds__(256) bpT2d_kernel(Geom2D g, const float2 *__restrict__ views,
+                                                    const TI *__restrict__ img, float *__restrict__ sino)
+{
+    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int b = blockIdx.z;
+    if (ix >= g.nx || iy >= g.ny)
+        return;
+    const float val = load_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix);
+    if (val == 0.0f)
+        return;
+    float *sb = sino + (size_t)b * g.n_proj * g.nu;
+    const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
+    const float rdu = 1.0f / g.du;
+    for (int k = 0; k < g.n_proj; ++k) {
+        const float2 c = views[k];
+        const float xu = -x * c.y + y * c.x;
+        float su, wt;
+        if (!FAN) {
+            su = fmaf(xu, rdu, g.cu);
+            wt = 1.0f;
+        } else {
+            const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
+            const float rw = 1.0f / w;
+            su = fmaf(g.sdd * xu * rw, rdu, g.cu);
+            const float sw = g.sid * rw;
+            wt = sw * sw;
+        }
+        const float fu = floorf(su);
+        const int j = (int)fu;
+        const float t = su - fu;
+        const float v = g.dbeta * wt * val;
+        if (j >= 0 && j < g.nu)
+            unsafeAtomicAdd(sb + (size_t)k * g.nu + j, v * (1.0f - t));
+        if (j + 1 >= 0 && j + 1 < g.nu)
+            unsafeAtomicAdd(sb + (size_t)k * g.nu + j + 1, v * t);
+    }
+}
+
+// --------------------------------------------------------------- B^T, 3D
+
+constexpr int BT_NZ = 16;
+constexpr int BT_TW = 64, BT_TH = 64;
+
+template <typename TI, bool AXIAL>
+__global__ void __launch_bounds__(256) bpT_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                       const TI *__restrict__ vol, float *__restrict__ proj, int nbx,
+                                                       int nby, int nzb)
+{
+    __shared__ float tile[BT_TH * BT_TW];
+    const int tid = threadIdx.x;
+    const int bxi = (int)(blockIdx.x % (unsigned)nbx), byi = (int)((blockIdx.x / (unsigned)nbx) % (unsigned)nby);
+    const int bzb = (int)(blockIdx.x / (unsigned)(nbx * nby));
+    const int zb = bzb % nzb, b = bzb / nzb;
+    const int ix = bxi * 16 + (tid & 15), iy = byi * 16 + (tid >> 4);
+    const int z0 = zb * BT_NZ;
+    const int zcount = min(BT_NZ, g.nz - z0);
+    const bool active = ix < g.nx && iy < g.ny;
+    const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
+    const float xc = (float)ix - hx, yc = (float)iy - hy, zc0 = (float)z0 - hz;
+    const int corner = tid & 7;
+    const float cx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) : bxi * 16) - hx;
+    const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
+    const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
+
+    float val[BT_NZ];
+    const TI *src = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)(active ? iy : 0) * g.nx + (active ? ix : 0);
+#pragma unroll
+    for (int z = 0; z < BT_NZ; ++z)
+        val[z] = (active && z < zcount) ? g.dbeta * load_f32(src + (size_t)(z0 + z) * g.ny * g.nx) : 0.0f;
+    float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
+
+    for (int k = 0; k < g.n_proj; ++k) {
+        const ConeBPView v = views[k];
+        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
+        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
+        const int u_lo = (int)floorf(min8(cu) + g.cu) - 1, u_hi = (int)floorf(max8(cu) + g.cu) + 2;
+        const int v_lo = (int)floorf(min8(cv) + g.cv) - 1, v_hi = (int)floorf(max8(cv) + g.cv) + 2;
+        const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
+        const bool staged = tw <= BT_TW && th <= BT_TH;
+        float *qk = pb + (size_t)k * g.nv * g.nu;
+        if (staged) {
+            __syncthreads();   // previous tile flushed
+            for (int i = tid; i < tw * th; i += 256)
+                tile[(i / tw) * BT_TW + (i % tw)] = 0.0f;
+            __syncthreads();
+        }
+        if (active) {
+#pragma unroll
+            for (int z = 0; z < BT_NZ; ++z) {
+                if (z >= zcount)
+                    continue;
+                const float zc = zc0 + (float)z;
+                const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
+                const float sw = g.sid * rW;
+                const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu, sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
+                const float fu = floorf(su), fv = floorf(sv);
+                const int j = (int)fu, i = (int)fv;
+                const float tu = su - fu, tv = sv - fv;
+                const float x = val[z] * sw * sw;
+                const float w00 = x * (1.0f - tu) * (1.0f - tv), w01 = x * tu * (1.0f - tv);
+                const float w10 = x * (1.0f - tu) * tv, w11 = x * tu * tv;
+                if (staged) {
+                    float *p = tile + (i - v_lo) * BT_TW + (j - u_lo);
+                    atomicAdd(p, w00);
+                    atomicAdd(p + 1, w01);
+                    atomicAdd(p + BT_TW, w10);
+                    atomicAdd(p + BT_TW + 1, w11);
+                } else {
+                    if ((unsigned)i < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
+                        unsafeAtomicAdd(qk + (size_t)i * g.nu + j, w00);
+                    if ((unsigned)i < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
+                        unsafeAtomicAdd(qk + (size_t)i * g.nu + j + 1, w01);
+                    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
+                        unsafeAtomicAdd(qk + (size_t)(i + 1) * g.nu + j, w10);
+                    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
+                        unsafeAtomicAdd(qk + (size_t)(i + 1) * g.nu + j + 1, w11);
+                }
+            }
+        }
+        if (staged) {
+            __syncthreads();
+            for (int idx = tid; idx < tw * th; idx += 256) {
+                const int r = idx / tw, c = idx - r * tw;
+                const int gi = v_lo + r, gj = u_lo + c;
+                const float t = tile[r * BT_TW + c];
+                if (t != 0.0f && (unsigned)gi < (unsigned)g.nv && (unsigned)gj < (unsigned)g.nu)
+                    unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
+            }
+        }
+    }
+}
+
+template <typename T, typename TI>
+hipError_t fpT2d(bool fan, const Geom2D &g, const float2 *views, const void *sino, void *img, int batch,
+                 hipStream_t s)
+{
+    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
+    if (fan)
+        hipLaunchKernelGGL((fpT2d_kernel<T, TI, true>), grid, dim3(256), 0, s, g, views, (const TI *)sino, (T *)img);
+    else
+        hipLaunchKernelGGL((fpT2d_kernel<T, TI, false>), grid, dim3(256), 0, s, g, views, (const TI *)sino, (T *)img);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fpT_cone(const Geom3D &g, const ConeFPView *fviews, const ConeBPView *bviews, const void *proj, void *vol,
+                    int batch, hipStream_t s)
+{
+    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + AT_NZ - 1) / AT_NZ;
+    hipLaunchKernelGGL((fpT_cone_kernel<T, T>), dim3((unsigned)(nbx * nby * nzb * batch)), dim3(256), 0, s, g, fviews,
+                       bviews, (const T *)proj, (T *)vol, nbx, nby, nzb);
+    return hipGetLastError();
+}
+
+hipError_t zero(float *p, size_t n, hipStream_t s)
+{
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project_adjoint_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
+                                     void *img, int batch, hipStream_t stream)
+{
+    switch (dtype) {
+    case 0: return fpT2d<float, float>(fan, g, views, sino, img, batch, stream);
+    case 1: return fpT2d<f16_t, f16_t>(fan, g, views, sino, img, batch, stream);
+    default: return fpT2d<bf16_t, bf16_t>(fan, g, views, sino, img, batch, stream);
+    }
+}
+
+hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPView *fviews,
+                                       const ConeBPView *bviews, const void *proj, void *vol, int batch,
+                                       hipStream_t stream)
+{
+    switch (dtype) {
+    case 0: return fpT_cone<float>(g, fviews, bviews, proj, vol, batch, stream);
+    case 1: return fpT_cone<f16_t>(g, fviews, bviews, proj, vol, batch, stream);
+    default: return fpT_cone<bf16_t>(g, fviews, bviews, proj, vol, batch, stream);
+    }
+}
+
+hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
+                                         float *sino, int batch, hipStream_t stream)
+{
+    hipError_t e = zero(sino, (size_t)batch * g.n_proj * g.nu, stream);
+    if (e != hipSuccess)
+        return e;
+    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
+    if (fan)
+        hipLaunchKernelGGL((bpT2d_kernel<float, true>), grid, dim3(256), 0, stream, g, views, img, sino);
+    else
+        hipLaunchKernelGGL((bpT2d_kernel<float, false>), grid, dim3(256), 0, stream, g, views, img, sino);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, const float *vol,
+                                           float *proj, int batch, hipStream_t stream)
+{
+    hipError_t e = zero(proj, (size_t)batch * g.n_proj * g.nv * g.nu, stream);
+    if (e != hipSuccess)
+        return e;
+    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + BT_NZ - 1) / BT_NZ;
+    const dim3 grid((unsigned)(nbx * nby * nzb * batch));
+    if (axial)
+        hipLaunchKernelGGL((bpT_cone_kernel<float, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                           nzb);
+    else
+        hipLaunchKernelGGL((bpT_cone_kernel<float, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                           nzb);
+    return hipGetLastError();
+}
+
+}  // namespace ph

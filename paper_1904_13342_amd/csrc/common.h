@@ -85,10 +85,22 @@ hipError_t launch_backproject_2d(int dtype, bool fan, const Geom2D &g, const flo
                                  bool sino_is_f32, void *img, int batch, hipStream_t stream);
 hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const void *vol, void *proj,
                                int batch, hipStream_t stream);
-// nz_seg: voxels per thread column segment (16, 32 or 64), chosen by the host
+// nz_seg: voxels per thread column segment (16 or 32), chosen by the host
 // so that a brick's detector footprint fits the LDS tile (64 x 128 pixels).
 hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
                                    const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream);
+
+// Exact transposes.  A^T: any storage type (gather, written once).  B^T:
+// FP32 in and out (scatter with float atomics into a zero-filled output).
+hipError_t launch_project_adjoint_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
+                                     void *img, int batch, hipStream_t stream);
+hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPView *fviews,
+                                       const ConeBPView *bviews, const void *proj, void *vol, int batch,
+                                       hipStream_t stream);
+hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
+                                         float *sino, int batch, hipStream_t stream);
+hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, const float *vol,
+                                           float *proj, int batch, hipStream_t stream);
 
 // Row filter: rows of length nu (count = batch * n_proj * nv) are weighted by
 // W_red[view][u] * W_cos[v][u] * W[v][u] (any of the three may be NULL; the

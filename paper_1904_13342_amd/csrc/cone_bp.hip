@@ -1,8 +1,8 @@
 // Voxel-driven, distance-weighted cone-beam back-projection from projection
 // matrices (Sec. II.B.2; Eq. 5's A^T in the FDK network).
 //
-// Mapping: a workgroup owns a 16 x 16 x NZ brick of voxels (NZ = 16, 32 or
-// 64, the deepest whose footprint fits the LDS tile); each thread owns
+// Mapping: a workgroup owns a 16 x 16 x NZ brick of voxels (NZ = 16 or 32,
+// the deeper one when its footprint fits the LDS tile); each thread owns
 // one (x, y) column segment of NZ voxels and accumulates it in registers over
 // all views, so the volume is written exactly once.  Per view, the brick's
 // footprint on the detector (bounded by the projections of its 8 corners,
@@ -15,7 +15,7 @@
 // the u and w rows) the column coordinate, the depth w and the weight are
 // constant along a column, and only the row coordinate moves with z: one FMA
 // per voxel.  General matrices take the per-voxel path.
-#include "common.h"
+#include "device_util.h"
 
 namespace ph {
 namespace {
@@ -27,40 +27,6 @@ template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
 {
     return (i >= 0 && j >= 0 && i < nv && j < nu) ? load_f32(q + (size_t)i * nu + j) : 0.0f;
-}
-
-__device__ __forceinline__ float dot4(const float r[4], float x, float y, float z)
-{
-    return fmaf(r[0], x, fmaf(r[1], y, fmaf(r[2], z, r[3])));
-}
-
-// 1/x from the hardware estimate refined by one Newton step
-__device__ __forceinline__ float rcp_nr(float x)
-{
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float x)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// min / max over the 8 lanes of each group {l : l mod 8 fixed... } holding
-// the 8 corners: xor 1 and xor 2 within quads, then rotate a row by 4 lanes
-// (pairs a quad of corners 0-3 with one of corners 4-7).
-__device__ __forceinline__ float min8(float x)
-{
-    x = fminf(x, dpp<0xB1>(x));
-    x = fminf(x, dpp<0x4E>(x));
-    return fminf(x, dpp<0x124>(x));
-}
-__device__ __forceinline__ float max8(float x)
-{
-    x = fmaxf(x, dpp<0xB1>(x));
-    x = fmaxf(x, dpp<0x4E>(x));
-    return fmaxf(x, dpp<0x124>(x));
 }
 
 // bilinear fetch at tile-local coordinates, unit-stride columns
@@ -91,13 +57,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
     __shared__ float tile[BP_TH * BP_TW];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
-    // Workgroups are handed to the 8 XCDs round-robin by linear id; remap so
-    // that each XCD takes a contiguous run of bricks in z-major order, i.e. a
-    // z slab, whose detector-row band then stays in that XCD's L2.
-    const unsigned total = gridDim.x;
-    unsigned lin = blockIdx.x;
-    if (lin < total - total % 8u)
-        lin = (lin % 8u) * (total / 8u) + lin / 8u;
+    const unsigned lin = blockIdx.x;
     const int bxi = (int)(lin % (unsigned)nbx), byi = (int)((lin / (unsigned)nbx) % (unsigned)nby);
     const int bzb = (int)(lin / (unsigned)(nbx * nby));
     const int ix = bxi * 16 + tx;
@@ -235,8 +195,6 @@ template <typename T, typename TI>
 hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg, const void *proj, void *vol,
                    int batch, hipStream_t s)
 {
-    if (nz_seg >= 64)
-        return bp_cone_nz<T, TI, 64>(g, views, axial, proj, vol, batch, s);
     if (nz_seg >= 32)
         return bp_cone_nz<T, TI, 32>(g, views, axial, proj, vol, batch, s);
     return bp_cone_nz<T, TI, 16>(g, views, axial, proj, vol, batch, s);

@@ -15,7 +15,7 @@
 // belongs to exactly one slab, decided by the same FP32 coordinate the
 // interpolation uses.  Slabs that do not fit in LDS, and tiles whose rays do
 // not share a dominant axis, read the volume directly.
-#include "common.h"
+#include "device_util.h"
 
 namespace ph {
 namespace {
@@ -23,7 +23,7 @@ namespace {
 constexpr int FP_TILE = 16;            // detector tile edge (pixels)
 constexpr int FP_D = 8;                // slab depth (planes along A)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
-constexpr int FP_LDS_FLOATS = 10240;   // 40 KiB slab capacity
+constexpr int FP_LDS_FLOATS = 9984;    // 39 KiB slab capacity: four workgroups per CU
 constexpr int FP_BIAS = 4;             // keeps biased coordinates positive (floor == truncation)
 
 template <typename T>
@@ -42,37 +42,6 @@ __device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float
     lo = fmaxf(lo, fminf(t1, t2));
     hi = fminf(hi, fmaxf(t1, t2));
     return true;
-}
-
-// Index coordinates (x, y, z) of a ray's anchor (its point closest to the
-// isocentre) and of one sampling step.
-struct Ray {
-    float p[3], e[3];
-};
-
-// Ray of detector pixel (j, i), set up in double precision (the source is
-// ~SID away, so an FP32 direction would misplace the ray by ~SID * 2^-24 at
-// the volume) and rounded once to FP32.
-__device__ __forceinline__ Ray make_ray(const Geom3D &g, const ConeFPView &v, int j, int i)
-{
-    const double jc = (double)j - (double)g.cu, ic = (double)i - (double)g.cv;
-    double d[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-        d[t] = fma(jc, v.du[t], fma(ic, v.dv[t], v.d0[t]));
-    const double rn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-        d[t] *= rn;
-    const double t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
-    const double o[3] = {g.ox, g.oy, g.oz}, s[3] = {g.sx, g.sy, g.sz};
-    Ray r;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        r.p[t] = (float)((fma(t0, d[t], v.s[t]) - o[t]) / s[t]);
-        r.e[t] = (float)((double)g.step * d[t] / s[t]);
-    }
-    return r;
 }
 
 template <typename T>
@@ -149,6 +118,12 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
     __syncthreads();
     const int s_min = s_range[0], s_max = s_range[1];
 
+    float rA[4];   // 1 / (A step) of the corner rays
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        rA[c] = 1.0f / cr[c].e[AX];
+    const float rEA = 1.0f / eA;
+
     float acc = 0.0f;
     int m = kb;   // next sample of this ray
     for (int n = 0; n <= s_max - s_min; ++n) {
@@ -160,7 +135,7 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
         for (int c = 0; c < 4; ++c) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                const float t = ((float)(a0 + e * FP_D) - cr[c].p[AX]) / cr[c].e[AX];
+                const float t = ((float)(a0 + e * FP_D) - cr[c].p[AX]) * rA[c];
                 const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
                 bmin = fminf(bmin, bb);
                 bmax = fmaxf(bmax, bb);
@@ -192,10 +167,22 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
                 const T *src = f + (size_t)(in_xy ? gy : 0) * g.nx + (in_xy ? gx : 0);
                 float *dst = slab + ib * FP_WA + ia;
                 const size_t zstride = (size_t)g.nx * g.ny;
-                for (int ic = 0; ic < HC; ++ic) {
-                    const int gz = c_lo + ic;
-                    dst[ic * plane] = (in_xy && (unsigned)gz < (unsigned)g.nz) ? load_f32(src + (size_t)gz * zstride)
-                                                                                : 0.0f;
+                // eight z planes at a time: the loads are unconditional (from
+                // a valid address) and issue back to back, the out-of-grid
+                // ones are zeroed afterwards
+                for (int ic0 = 0; ic0 < HC; ic0 += 8) {
+                    float vals[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int gz = c_lo + ic0 + u;
+                        const bool ok = in_xy && ic0 + u < HC && (unsigned)gz < (unsigned)g.nz;
+                        const float val = load_f32(src + (ok ? (size_t)gz * zstride : (size_t)0));
+                        vals[u] = ok ? val : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (ic0 + u < HC)
+                            dst[(ic0 + u) * plane] = vals[u];
                 }
             }
             __syncthreads();
@@ -208,7 +195,7 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
         int m_end = m;
         if (m <= ke && in_slab(m, eA, PA0, offA)) {
             const float bound = sgn > 0.0f ? (float)(offA + FP_D) : (float)offA;
-            const float est = (bound - fmaf((float)m, eA, PA0)) / eA;
+            const float est = (bound - fmaf((float)m, eA, PA0)) * rEA;
             m_end = min(m + max((int)ceilf(est), 1), ke + 1);
             while (m_end > m + 1 && !in_slab(m_end - 1, eA, PA0, offA))
                 --m_end;
@@ -255,7 +242,7 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     const ConeFPView &v = views[k];
     const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;
 
-    const Ray r = make_ray(g, v, valid ? j : j0, valid ? i : i0);
+    const Ray r = make_cone_ray(g, v, valid ? j : j0, valid ? i : i0);
     float lo = -3.0e38f, hi = 3.0e38f;
     const bool hit = valid && krange(r.p[0], r.e[0], g.nx, lo, hi) && krange(r.p[1], r.e[1], g.ny, lo, hi) &&
                      krange(r.p[2], r.e[2], g.nz, lo, hi) && lo < hi;
@@ -265,10 +252,10 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     // the tile's four corner rays bound the pyramid of its rays
     const int jh = min(j0 + FP_TILE - 1, g.nu - 1), ih = min(i0 + FP_TILE - 1, g.nv - 1);
     Ray cr[4];
-    cr[0] = make_ray(g, v, j0, i0);
-    cr[1] = make_ray(g, v, jh, i0);
-    cr[2] = make_ray(g, v, j0, ih);
-    cr[3] = make_ray(g, v, jh, ih);
+    cr[0] = make_cone_ray(g, v, j0, i0);
+    cr[1] = make_cone_ray(g, v, jh, i0);
+    cr[2] = make_cone_ray(g, v, j0, ih);
+    cr[3] = make_cone_ray(g, v, jh, ih);
     const int ax = fabs(v.d0[0]) >= fabs(v.d0[1]) ? 0 : 1;
     // every ray must advance along A in one direction, at least as fast as
     // across it, and by at most one voxel per step (margin samples stay

@@ -1,0 +1,117 @@
+// Device helpers shared by the projector, back-projector and adjoint kernels.
+#pragma once
+
+#include "common.h"
+
+namespace ph {
+
+// Index coordinates (x, y, z) of a ray's anchor (its point closest to the
+// isocentre) and of one sampling step: sample m sits at p + m * e.
+struct Ray {
+    float p[3], e[3];
+};
+
+// Ray of cone-beam detector pixel (j, i), set up in double precision (the
+// source is ~SID away, so an FP32 direction would misplace the ray by
+// ~SID * 2^-24 at the volume) and rounded once to FP32.  The forward
+// projector and its transpose both use this, so they see the same samples.
+__device__ __forceinline__ Ray make_cone_ray(const Geom3D &g, const ConeFPView &v, int j, int i)
+{
+    const double jc = (double)j - (double)g.cu, ic = (double)i - (double)g.cv;
+    double d[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        d[t] = fma(jc, v.du[t], fma(ic, v.dv[t], v.d0[t]));
+    const double rn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        d[t] *= rn;
+    const double t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
+    const double o[3] = {g.ox, g.oy, g.oz}, s[3] = {g.sx, g.sy, g.sz};
+    Ray r;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        r.p[t] = (float)((fma(t0, d[t], v.s[t]) - o[t]) / s[t]);
+        r.e[t] = (float)((double)g.step * d[t] / s[t]);
+    }
+    return r;
+}
+
+// Ray of 2D detector bin j in a view with central ray vector c: index
+// coordinates (x, y) of its anchor and of one step (fan rays set up in double
+// precision for the same reason as cone rays).
+template <bool FAN>
+__device__ __forceinline__ void make_ray_2d(const Geom2D &g, float2 c, int j, float &X0, float &Y0, float &eX,
+                                            float &eY)
+{
+    const double cx = c.x, cy = c.y, ex = -cy, ey = cx;
+    const double u = ((double)j - (double)g.cu) * (double)g.du;
+    double ax, ay, dx, dy;
+    if (!FAN) {
+        ax = u * ex;
+        ay = u * ey;
+        dx = cx;
+        dy = cy;
+    } else {
+        const double sx = -(double)g.sid * cx, sy = -(double)g.sid * cy;
+        const double tx = (double)g.sdd * cx + u * ex, ty = (double)g.sdd * cy + u * ey;  // detector - source
+        const double rn = 1.0 / sqrt(tx * tx + ty * ty);
+        dx = tx * rn;
+        dy = ty * rn;
+        const double t0 = -(sx * dx + sy * dy);
+        ax = fma(t0, dx, sx);
+        ay = fma(t0, dy, sy);
+    }
+    X0 = (float)((ax - (double)g.ox) / (double)g.sx);
+    Y0 = (float)((ay - (double)g.oy) / (double)g.sy);
+    eX = (float)((double)g.step * dx / (double)g.sx);
+    eY = (float)((double)g.step * dy / (double)g.sy);
+}
+
+// Narrow [lo, hi] to the parameters t with p + t e inside the open interval
+// (a, b); false if the line never enters it.
+__device__ __forceinline__ bool clip_line(float p, float e, float a, float b, float &lo, float &hi)
+{
+    if (fabsf(e) < 1e-30f)
+        return p > a && p < b;
+    const float t1 = (a - p) / e, t2 = (b - p) / e;
+    lo = fmaxf(lo, fminf(t1, t2));
+    hi = fminf(hi, fmaxf(t1, t2));
+    return true;
+}
+
+__device__ __forceinline__ float dot4(const float r[4], float x, float y, float z)
+{
+    return fmaf(r[0], x, fmaf(r[1], y, fmaf(r[2], z, r[3])));
+}
+
+// 1/x from the hardware estimate refined by one Newton step
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// min / max over the 8 corners held by lanes with corner index lane mod 8:
+// xor 1 and xor 2 within quads, then rotate each 16-lane row by 4 lanes,
+// which pairs a quad holding corners 0-3 with one holding corners 4-7.
+__device__ __forceinline__ float min8(float x)
+{
+    x = fminf(x, dpp<0xB1>(x));
+    x = fminf(x, dpp<0x4E>(x));
+    return fminf(x, dpp<0x124>(x));
+}
+__device__ __forceinline__ float max8(float x)
+{
+    x = fmaxf(x, dpp<0xB1>(x));
+    x = fmaxf(x, dpp<0x4E>(x));
+    return fmaxf(x, dpp<0x124>(x));
+}
+
+}  // namespace ph

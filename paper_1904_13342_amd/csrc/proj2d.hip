@@ -2,7 +2,7 @@
 // detector bin) and back-projection (voxel-driven, one thread per pixel),
 // Sec. II.B.2.  The images of the 2D workloads (at most 512 x 512 FP32,
 // 1 MiB) stay resident in L2, so both kernels read global memory directly.
-#include "common.h"
+#include "device_util.h"
 
 namespace ph {
 namespace {
@@ -11,33 +11,6 @@ template <typename T>
 __device__ __forceinline__ float pix(const T *img, int nx, int ny, int ix, int iy)
 {
     return (ix >= 0 && iy >= 0 && ix < nx && iy < ny) ? load_f32(img + (size_t)iy * nx + ix) : 0.0f;
-}
-
-// Ray of bin j in a view with central ray vector c: anchor a (point closest to
-// the isocentre) and unit direction d, world mm.  Fan rays are set up in
-// double precision: the source sits ~SID from the image, so an FP32 direction
-// would misplace the ray by ~SID * 2^-24 there.
-template <bool FAN>
-__device__ __forceinline__ void ray2d(const Geom2D &g, float2 c, int j, double &ax, double &ay, double &dx,
-                                      double &dy)
-{
-    const double cx = c.x, cy = c.y, ex = -cy, ey = cx;
-    const double u = ((double)j - (double)g.cu) * (double)g.du;
-    if (!FAN) {
-        ax = u * ex;
-        ay = u * ey;
-        dx = cx;
-        dy = cy;
-    } else {
-        const double sx = -(double)g.sid * cx, sy = -(double)g.sid * cy;
-        const double tx = (double)g.sdd * cx + u * ex, ty = (double)g.sdd * cy + u * ey;  // detector - source
-        const double rn = 1.0 / sqrt(tx * tx + ty * ty);
-        dx = tx * rn;
-        dy = ty * rn;
-        const double t0 = -(sx * dx + sy * dy);
-        ax = fma(t0, dx, sx);
-        ay = fma(t0, dy, sy);
-    }
 }
 
 // Integer sample range covering the open box (-1, n) in index coordinates,
@@ -62,10 +35,8 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
     if (j >= g.nu)
         return;
     const T *im = img + (size_t)b * g.nx * g.ny;
-    double ax, ay, dx, dy;
-    ray2d<FAN>(g, views[k], j, ax, ay, dx, dy);
-    const float X0 = (float)((ax - (double)g.ox) / (double)g.sx), Y0 = (float)((ay - (double)g.oy) / (double)g.sy);
-    const float eX = (float)((double)g.step * dx / (double)g.sx), eY = (float)((double)g.step * dy / (double)g.sy);
+    float X0, Y0, eX, eY;
+    make_ray_2d<FAN>(g, views[k], j, X0, Y0, eX, eY);
     float lo = -3.0e38f, hi = 3.0e38f;
     float acc = 0.0f;
     if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && lo < hi) {

@@ -183,6 +183,32 @@ def backproject_cone3d(g, mats, proj, out=None):
     return _unary("ph_backproject_cone3d", g, mats, proj, _sino_tail(g), _vol_tail(g), out)
 
 
+def project_adjoint_par2d(g, ray_vecs, sino, out=None):
+    """A^T of project_par2d (exact transpose)."""
+    return _unary("ph_project_adjoint_par2d", g, ray_vecs, sino, _sino_tail(g), _vol_tail(g), out)
+
+
+def project_adjoint_fan2d(g, ray_vecs, sino, out=None):
+    return _unary("ph_project_adjoint_fan2d", g, ray_vecs, sino, _sino_tail(g), _vol_tail(g), out)
+
+
+def project_adjoint_cone3d(g, mats, proj, out=None):
+    return _unary("ph_project_adjoint_cone3d", g, mats, proj, _sino_tail(g), _vol_tail(g), out)
+
+
+def backproject_adjoint_par2d(g, ray_vecs, img, out=None):
+    """B^T of backproject_par2d (exact transpose; FP32 only)."""
+    return _unary("ph_backproject_adjoint_par2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+
+
+def backproject_adjoint_fan2d(g, ray_vecs, img, out=None):
+    return _unary("ph_backproject_adjoint_fan2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+
+
+def backproject_adjoint_cone3d(g, mats, vol, out=None):
+    return _unary("ph_backproject_adjoint_cone3d", g, mats, vol, _vol_tail(g), _sino_tail(g), out)
+
+
 def _filter_len(K, M):
     if K is not None:
         return K.numel() if M in (None, 0) else M
@@ -276,8 +302,10 @@ def version():
 
 
 __all__ = [
-    "geom2d", "geom3d", "from_spec", "ray_vectors_2d", "projection_matrices_3d", "project_par2d",
+    "Geom2D", "Geom3D", "geom2d", "geom3d", "from_spec", "ray_vectors_2d", "projection_matrices_3d", "project_par2d",
     "project_fan2d", "project_cone3d", "backproject_par2d", "backproject_fan2d", "backproject_cone3d",
+    "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
+    "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
     "fbp_fan2d", "fdk_cone3d", "version",
 ]

@@ -1,0 +1,118 @@
+"""Reduced-precision storage: volumes and projections stored as FP16 or BF16,
+all arithmetic in FP32, geometry in FP32.
+
+The oracle runs in FP64 on the dequantised half-precision input, so the
+difference measures the kernel (FP32 arithmetic plus rounding of the output to
+the storage type, rel-L2 about u/sqrt(3): 2.8e-4 for FP16, 2.3e-3 for BF16).
+Bounds: 2e-3 for FP16; BF16's own rounding already exceeds that, so its bound
+is 1e-2 and the value is printed.  The end-to-end error against FP64 on the
+unquantised input is printed beside it."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gpu_common as gc
+import synth
+from gpu_common import as_f32, rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {torch.float16: 2e-3, torch.bfloat16: 1e-2}
+DTYPES = [torch.float16, torch.bfloat16]
+
+
+@pytest.fixture(scope="module")
+def ph():
+    gc.device()
+    import paper_1904_13342_amd as ph
+    return ph
+
+
+def quantise(a, dtype):
+    """Round to the storage type (round to nearest even) and back to float64."""
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(dtype).to(torch.float64).numpy()
+
+
+SPEC_3D = synth.config("cone3d_crop32").with_(vol_shape=(29, 33, 31), n_proj=40,
+                                               angular_range=200 * math.pi / 180)
+SPEC_2D = synth.config("fan2d_512").with_(vol_shape=(96, 80), vol_spacing=(1.0, 1.0), det_shape=(151,),
+                                          det_spacing=(1.2,), n_proj=60, sid=200.0, sdd=320.0)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
+def test_project_cone_half(ph, ora, dtype):
+    spec = SPEC_3D
+    f = gc.phantom(spec)
+    fq = quantise(f, dtype)
+    g = ph.from_spec(spec)
+    out = ph.project_cone3d(g, ph.projection_matrices_3d(g), to_dev(fq, dtype))
+    assert out.dtype == dtype
+    ref = ora.project(spec, fq)
+    err = rel_l2(to_np(out), ref)
+    e2e = rel_l2(to_np(out), ora.project(spec, f))
+    say(f"[project_cone {dtype}] vs FP64 on stored input {err:.2e}; end to end {e2e:.2e}")
+    assert err < BOUND[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
+def test_backproject_and_fdk_cone_half(ph, ora, dtype):
+    spec = SPEC_3D
+    p = as_f32(ora.project(spec, gc.phantom(spec)))
+    pq = quantise(p, dtype)
+    g = ph.from_spec(spec)
+    mats = ph.projection_matrices_3d(g)
+    q = as_f32(ora.filter_projections(spec, ora.weight(spec, p)))
+    qq = quantise(q, dtype)
+    out = ph.backproject_cone3d(g, mats, to_dev(qq, dtype))
+    err = rel_l2(to_np(out), ora.backproject(spec, qq))
+    e2e = rel_l2(to_np(out), ora.backproject(spec, q))
+    say(f"[backproject_cone {dtype}] {err:.2e}; end to end {e2e:.2e}")
+    assert out.dtype == dtype and err < BOUND[dtype]
+    rec = ph.fdk_cone3d(g, mats, to_dev(pq, dtype))
+    err = rel_l2(to_np(rec), ora.fbp(spec, pq))
+    e2e = rel_l2(to_np(rec), ora.fbp(spec, p))
+    say(f"[fdk_cone {dtype}] {err:.2e}; end to end {e2e:.2e}")
+    assert rec.dtype == dtype and err < BOUND[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
+def test_fan2d_half(ph, ora, dtype):
+    spec = SPEC_2D
+    f = gc.phantom(spec)
+    fq = quantise(f, dtype)
+    g = ph.from_spec(spec)
+    rv = ph.ray_vectors_2d(g)
+    sino = ph.project_fan2d(g, rv, to_dev(fq, dtype))
+    err = rel_l2(to_np(sino), ora.project(spec, fq))
+    say(f"[project_fan2d {dtype}] {err:.2e}")
+    assert sino.dtype == dtype and err < BOUND[dtype]
+    sq = to_np(sino)
+    rec = ph.fbp_fan2d(g, rv, sino)
+    err = rel_l2(to_np(rec), ora.fbp(spec, sq))
+    e2e = rel_l2(to_np(rec), ora.fbp(spec, ora.project(spec, f)))
+    say(f"[fbp_fan2d {dtype}] {err:.2e}; end to end {e2e:.2e}")
+    assert rec.dtype == dtype and err < BOUND[dtype]
+
+
+def test_half_rounding_is_nearest_even(ph):
+    """Stored values equal torch's round-to-nearest-even conversion of the FP32
+    result: back-project an exactly representable input whose FP32 output
+    is known (a constant projection gives dbeta * sum_k (SID/w)^2 ...); here
+    we check the simplest exact case, the parallel-beam back-projection of a
+    constant sinogram, whose FP32 result is n_proj * dbeta * c."""
+    spec = synth.config("par2d_64").with_(n_proj=8, det_shape=(200,))
+    g = ph.from_spec(spec)
+    rv = ph.ray_vectors_2d(g)
+    for dtype in DTYPES:
+        sino = torch.full((spec.n_proj, spec.det_shape[0]), 0.3, dtype=dtype, device=gc.device())
+        img = ph.backproject_par2d(g, rv, sino)
+        c32 = float(torch.tensor(0.3, dtype=dtype).float())
+        dbeta = np.float32(spec.angular_range) / np.float32(spec.n_proj)
+        acc = np.float32(0.0)
+        for _ in range(spec.n_proj):
+            acc = np.float32(acc + np.float32(c32))
+        expect = torch.tensor(float(np.float32(dbeta) * acc), dtype=torch.float32).to(dtype)
+        centre = img[32, 32]
+        assert centre.item() == expect.item(), (dtype, centre.item(), expect.item())
