@@ -968,8 +968,8 @@ int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const v
     st = prep3d(g, mats, true, &G, &views, &axial);
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_adjoint_cone(G, (const ConeBPView *)views, axial, (const float *)vol,
-                                                     (float *)proj, batch, (hipStream_t)stream));
+    return to_status(launch_backproject_adjoint_cone(G, (const ConeBPView *)views, axial, bp_segment(g),
+                                                     (const float *)vol, (float *)proj, batch, (hipStream_t)stream));
 }
 
 }  // extern "C"

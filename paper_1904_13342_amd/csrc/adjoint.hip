@@ -12,11 +12,10 @@
 // LDS table shared by the block, and every thread accumulates its segment in
 // its own LDS slots.
 //
-// B^T, the transpose of the voxel-driven distance-weighted back-projector,
-// scatters each voxel's value times dbeta * weight into the four detector
-// pixels of its bilinear footprint: in 3D into an LDS tile of the brick's
-// footprint (LDS atomics), then one global float atomic per touched pixel;
-// in 2D straight into the sinogram.  Its output is FP32.
+// B^T in 2D, the transpose of the voxel-driven distance-weighted
+// back-projector, scatters each pixel's value times dbeta * weight into the
+// two detector bins of its linear footprint with float atomics (FP32 output);
+// the 3D B^T sits beside the back-projector it mirrors.
 #include "device_util.h"
 
 namespace ph {
@@ -180,9 +179,12 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
                 if (!clip_line(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) || !clip_line(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) ||
                     !clip_line(Z0, eZ, zlo, zhi, lo, hi) || !(lo < hi))
                     continue;
+                // the projector's biased sample positions, un-biased exactly
+                const float Xb = X0 + RAY_BIAS, Yb = Y0 + RAY_BIAS, Zb = Z0 + RAY_BIAS;
                 for (int m = (int)floorf(lo); m <= (int)ceilf(hi); ++m) {
-                    const float fm = (float)m;
-                    const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0), Z = fmaf(fm, eZ, Z0);
+                    const float X = ray_coord_biased(Xb, eX, m) - RAY_BIAS;
+                    const float Y = ray_coord_biased(Yb, eY, m) - RAY_BIAS;
+                    const float Z = ray_coord_biased(Zb, eZ, m) - RAY_BIAS;
                     const float w = gv * (1.0f - fabsf(X - fx)) * (1.0f - fabsf(Y - fy));
                     if (!(fabsf(X - fx) < 1.0f && fabsf(Y - fy) < 1.0f))
                         continue;
@@ -252,100 +254,6 @@ __global__ void __launch_bounds__(256) bpT2d_kernel(Geom2D g, const float2 *__re
     }
 }
 
-// --------------------------------------------------------------- B^T, 3D
-
-constexpr int BT_NZ = 16;
-constexpr int BT_TW = 64, BT_TH = 64;
-
-template <typename TI, bool AXIAL>
-__global__ void __launch_bounds__(256) bpT_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
-                                                       const TI *__restrict__ vol, float *__restrict__ proj, int nbx,
-                                                       int nby, int nzb)
-{
-    __shared__ float tile[BT_TH * BT_TW];
-    const int tid = threadIdx.x;
-    const int bxi = (int)(blockIdx.x % (unsigned)nbx), byi = (int)((blockIdx.x / (unsigned)nbx) % (unsigned)nby);
-    const int bzb = (int)(blockIdx.x / (unsigned)(nbx * nby));
-    const int zb = bzb % nzb, b = bzb / nzb;
-    const int ix = bxi * 16 + (tid & 15), iy = byi * 16 + (tid >> 4);
-    const int z0 = zb * BT_NZ;
-    const int zcount = min(BT_NZ, g.nz - z0);
-    const bool active = ix < g.nx && iy < g.ny;
-    const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
-    const float xc = (float)ix - hx, yc = (float)iy - hy, zc0 = (float)z0 - hz;
-    const int corner = tid & 7;
-    const float cx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) : bxi * 16) - hx;
-    const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
-    const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
-
-    float val[BT_NZ];
-    const TI *src = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)(active ? iy : 0) * g.nx + (active ? ix : 0);
-#pragma unroll
-    for (int z = 0; z < BT_NZ; ++z)
-        val[z] = (active && z < zcount) ? g.dbeta * load_f32(src + (size_t)(z0 + z) * g.ny * g.nx) : 0.0f;
-    float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
-
-    for (int k = 0; k < g.n_proj; ++k) {
-        const ConeBPView v = views[k];
-        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
-        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
-        const int u_lo = (int)floorf(min8(cu) + g.cu) - 1, u_hi = (int)floorf(max8(cu) + g.cu) + 2;
-        const int v_lo = (int)floorf(min8(cv) + g.cv) - 1, v_hi = (int)floorf(max8(cv) + g.cv) + 2;
-        const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
-        const bool staged = tw <= BT_TW && th <= BT_TH;
-        float *qk = pb + (size_t)k * g.nv * g.nu;
-        if (staged) {
-            __syncthreads();   // previous tile flushed
-            for (int i = tid; i < tw * th; i += 256)
-                tile[(i / tw) * BT_TW + (i % tw)] = 0.0f;
-            __syncthreads();
-        }
-        if (active) {
-#pragma unroll
-            for (int z = 0; z < BT_NZ; ++z) {
-                if (z >= zcount)
-                    continue;
-                const float zc = zc0 + (float)z;
-                const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
-                const float sw = g.sid * rW;
-                const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu, sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
-                const float fu = floorf(su), fv = floorf(sv);
-                const int j = (int)fu, i = (int)fv;
-                const float tu = su - fu, tv = sv - fv;
-                const float x = val[z] * sw * sw;
-                const float w00 = x * (1.0f - tu) * (1.0f - tv), w01 = x * tu * (1.0f - tv);
-                const float w10 = x * (1.0f - tu) * tv, w11 = x * tu * tv;
-                if (staged) {
-                    float *p = tile + (i - v_lo) * BT_TW + (j - u_lo);
-                    atomicAdd(p, w00);
-                    atomicAdd(p + 1, w01);
-                    atomicAdd(p + BT_TW, w10);
-                    atomicAdd(p + BT_TW + 1, w11);
-                } else {
-                    if ((unsigned)i < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
-                        unsafeAtomicAdd(qk + (size_t)i * g.nu + j, w00);
-                    if ((unsigned)i < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
-                        unsafeAtomicAdd(qk + (size_t)i * g.nu + j + 1, w01);
-                    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
-                        unsafeAtomicAdd(qk + (size_t)(i + 1) * g.nu + j, w10);
-                    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
-                        unsafeAtomicAdd(qk + (size_t)(i + 1) * g.nu + j + 1, w11);
-                }
-            }
-        }
-        if (staged) {
-            __syncthreads();
-            for (int idx = tid; idx < tw * th; idx += 256) {
-                const int r = idx / tw, c = idx - r * tw;
-                const int gi = v_lo + r, gj = u_lo + c;
-                const float t = tile[r * BT_TW + c];
-                if (t != 0.0f && (unsigned)gi < (unsigned)g.nv && (unsigned)gj < (unsigned)g.nu)
-                    unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
-            }
-        }
-    }
-}
-
 template <typename T, typename TI>
 hipError_t fpT2d(bool fan, const Geom2D &g, const float2 *views, const void *sino, void *img, int batch,
                  hipStream_t s)
@@ -368,14 +276,14 @@ hipError_t fpT_cone(const Geom3D &g, const ConeFPView *fviews, const ConeBPView 
     return hipGetLastError();
 }
 
-hipError_t zero(float *p, size_t n, hipStream_t s)
+}  // namespace
+
+hipError_t fill_zero(float *p, size_t n, hipStream_t s)
 {
     const size_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
-
-}  // namespace
 
 hipError_t launch_project_adjoint_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
                                      void *img, int batch, hipStream_t stream)
@@ -401,7 +309,7 @@ hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPV
 hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
                                          float *sino, int batch, hipStream_t stream)
 {
-    hipError_t e = zero(sino, (size_t)batch * g.n_proj * g.nu, stream);
+    hipError_t e = fill_zero(sino, (size_t)batch * g.n_proj * g.nu, stream);
     if (e != hipSuccess)
         return e;
     dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
@@ -409,23 +317,6 @@ hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2
         hipLaunchKernelGGL((bpT2d_kernel<float, true>), grid, dim3(256), 0, stream, g, views, img, sino);
     else
         hipLaunchKernelGGL((bpT2d_kernel<float, false>), grid, dim3(256), 0, stream, g, views, img, sino);
-    return hipGetLastError();
-}
-
-hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, const float *vol,
-                                           float *proj, int batch, hipStream_t stream)
-{
-    hipError_t e = zero(proj, (size_t)batch * g.n_proj * g.nv * g.nu, stream);
-    if (e != hipSuccess)
-        return e;
-    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + BT_NZ - 1) / BT_NZ;
-    const dim3 grid((unsigned)(nbx * nby * nzb * batch));
-    if (axial)
-        hipLaunchKernelGGL((bpT_cone_kernel<float, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                           nzb);
-    else
-        hipLaunchKernelGGL((bpT_cone_kernel<float, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                           nzb);
     return hipGetLastError();
 }
 

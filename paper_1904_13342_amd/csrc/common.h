@@ -99,8 +99,11 @@ hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPV
                                        hipStream_t stream);
 hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
                                          float *sino, int batch, hipStream_t stream);
-hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, const float *vol,
-                                           float *proj, int batch, hipStream_t stream);
+hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
+                                           const float *vol, float *proj, int batch, hipStream_t stream);
+// zero-fill kernel (used in place of a memset, which would not replay
+// correctly inside a captured graph)
+hipError_t fill_zero(float *p, size_t n, hipStream_t stream);
 
 // Row filter: rows of length nu (count = batch * n_proj * nv) are weighted by
 // W_red[view][u] * W_cos[v][u] * W[v][u] (any of the three may be NULL; the

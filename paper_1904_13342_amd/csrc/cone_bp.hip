@@ -11,6 +11,8 @@
 // corners are projected by eight lanes each and reduced across lanes with DPP
 // moves, so every wave gets the footprint without an extra barrier.
 //
+// The exact transpose B^T (below) mirrors this kernel.
+//
 // For a circular trajectory about z (AXIAL: the matrices have no z term in
 // the u and w rows) the column coordinate, the depth w and the weight are
 // constant along a column, and only the row coordinate moves with z: one FMA
@@ -176,6 +178,153 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
             store_f32(out + (size_t)(z0 + z) * g.ny * g.nx, g.dbeta * acc[z]);
 }
 
+// ------------------------------------------------------------------- B^T
+// Exact transpose of the kernel above: the same bricks, footprints and FP32
+// detector coordinates (so the pair is transposed to the last rounding of the
+// positions), with each voxel's value times dbeta * (SID/w)^2 splatted into
+// the four pixels of its bilinear footprint.  Splats go to an LDS tile of the
+// brick's footprint (LDS atomics); the tile is then added to the projections
+// with one global float atomic per pixel.  FP32 in and out; the output must be
+// zero on entry.
+
+__device__ __forceinline__ void splat_tile(float *p, float x, float fu, float fv)
+{
+    atomicAdd(p, x * (1.0f - fu) * (1.0f - fv));
+    atomicAdd(p + 1, x * fu * (1.0f - fv));
+    atomicAdd(p + BP_TW, x * (1.0f - fu) * fv);
+    atomicAdd(p + BP_TW + 1, x * fu * fv);
+}
+
+__device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su, float sv, float x)
+{
+    const float fsu = floorf(su), fsv = floorf(sv);
+    const int j = (int)fsu, i = (int)fsv;
+    const float fu = su - fsu, fv = sv - fsv;
+    if ((unsigned)i < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j, x * (1.0f - fu) * (1.0f - fv));
+    if ((unsigned)i < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j + 1, x * fu * (1.0f - fv));
+    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j, x * (1.0f - fu) * fv);
+    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j + 1, x * fu * fv);
+}
+
+template <int BP_NZ, bool AXIAL>
+__global__ void __launch_bounds__(256) bpT_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                       const float *__restrict__ vol, float *__restrict__ proj,
+                                                       int nbx, int nby, int nzb)
+{
+    __shared__ float tile[BP_TH * BP_TW];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const unsigned lin = blockIdx.x;
+    const int bxi = (int)(lin % (unsigned)nbx), byi = (int)((lin / (unsigned)nbx) % (unsigned)nby);
+    const int bzb = (int)(lin / (unsigned)(nbx * nby));
+    const int ix = bxi * 16 + tx;
+    const int iy = byi * 16 + ty;
+    const int zb = bzb % nzb, b = bzb / nzb;
+    const int z0 = zb * BP_NZ;
+    const int zcount = min(BP_NZ, g.nz - z0);
+    const bool active = ix < g.nx && iy < g.ny;
+
+    const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
+    const float xc = (float)ix - hx, yc = (float)iy - hy, zc0 = (float)z0 - hz;
+    const int corner = tid & 7;
+    const float cx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) : bxi * 16) - hx;
+    const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
+    const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
+
+    float val[BP_NZ];
+    const float *src = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)(active ? iy : 0) * g.nx + (active ? ix : 0);
+#pragma unroll
+    for (int z = 0; z < BP_NZ; ++z)
+        val[z] = (active && z < zcount) ? g.dbeta * src[(size_t)(z0 + z) * g.ny * g.nx] : 0.0f;
+    float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
+
+    for (int k = 0; k < g.n_proj; ++k) {
+        const ConeBPView v = views[k];
+        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
+        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
+        const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
+        const int u_lo = (int)floorf(umin + g.cu) - 1, u_hi = (int)floorf(umax + g.cu) + 2;
+        const int v_lo = (int)floorf(vmin + g.cv) - 1, v_hi = (int)floorf(vmax + g.cv) + 2;
+        const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
+        const bool staged = tw <= BP_TW && th <= BP_TH;
+        float *qk = pb + (size_t)k * g.nv * g.nu;
+        if (staged) {
+            __syncthreads();   // the previous tile has been flushed
+            for (int r = ty; r < th; r += 16)
+                for (int c = tx; c < tw; c += 16)
+                    tile[r * BP_TW + c] = 0.0f;
+            __syncthreads();
+        }
+        if (active) {
+            if (AXIAL) {
+                const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc0));
+                const float sw = g.sid * rW, wt = sw * sw;
+                const float uc = dot4(v.r[0], xc, yc, zc0) * rW;
+                const float vc0 = dot4(v.r[1], xc, yc, zc0) * rW;
+                const float dvz = v.r[1][2] * rW;
+                if (staged) {
+                    const float su = uc + g.cu - (float)u_lo;
+                    const float sv0 = vc0 + g.cv - (float)v_lo;
+                    const int iu = (int)su;
+                    const float fu = __builtin_amdgcn_fractf(su);
+                    float *col = tile + iu;
+#pragma unroll
+                    for (int z = 0; z < BP_NZ; ++z) {
+                        if (z < zcount) {
+                            const float sv = fmaf((float)z, dvz, sv0);
+                            const int iv = (int)sv;
+                            splat_tile(col + iv * BP_TW, wt * val[z], fu, __builtin_amdgcn_fractf(sv));
+                        }
+                    }
+                } else {
+                    const float su = uc + g.cu, sv0 = vc0 + g.cv;
+#pragma unroll
+                    for (int z = 0; z < BP_NZ; ++z)
+                        if (z < zcount)
+                            splat_global(qk, g, su, fmaf((float)z, dvz, sv0), wt * val[z]);
+                }
+            } else {
+#pragma unroll
+                for (int z = 0; z < BP_NZ; ++z) {
+                    if (z < zcount) {
+                        const float zc = zc0 + (float)z;
+                        const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
+                        const float sw = g.sid * rW, wt = sw * sw;
+                        const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
+                        const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
+                        if (staged) {
+                            const float lu = su - (float)u_lo, lv = sv - (float)v_lo;
+                            const int iu = (int)lu, iv = (int)lv;
+                            splat_tile(tile + iv * BP_TW + iu, wt * val[z], __builtin_amdgcn_fractf(lu),
+                                       __builtin_amdgcn_fractf(lv));
+                        } else {
+                            splat_global(qk, g, su, sv, wt * val[z]);
+                        }
+                    }
+                }
+            }
+        }
+        if (staged) {
+            __syncthreads();
+            for (int r = ty; r < th; r += 16) {
+                const int gi = v_lo + r;
+                if ((unsigned)gi >= (unsigned)g.nv)
+                    continue;
+                for (int c = tx; c < tw; c += 16) {
+                    const int gj = u_lo + c;
+                    const float t = tile[r * BP_TW + c];
+                    if (t != 0.0f && (unsigned)gj < (unsigned)g.nu)
+                        unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
+                }
+            }
+        }
+    }
+}
+
 template <typename T, typename TI, int NZ>
 hipError_t bp_cone_nz(const Geom3D &g, const ConeBPView *views, bool axial, const void *proj, void *vol, int batch,
                       hipStream_t s)
@@ -214,6 +363,33 @@ hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView 
         return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, axial, nz_seg, proj, vol, batch, stream)
                            : bp_cone<bf16_t, bf16_t>(g, views, axial, nz_seg, proj, vol, batch, stream);
     }
+}
+
+hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
+                                           const float *vol, float *proj, int batch, hipStream_t stream)
+{
+    hipError_t e = fill_zero(proj, (size_t)batch * g.n_proj * g.nv * g.nu, stream);
+    if (e != hipSuccess)
+        return e;
+    const int NZ = nz_seg >= 32 ? 32 : 16;
+    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
+    const dim3 grid((unsigned)(nbx * nby * nzb * batch));
+    if (NZ == 32) {
+        if (axial)
+            hipLaunchKernelGGL((bpT_cone_kernel<32, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                               nzb);
+        else
+            hipLaunchKernelGGL((bpT_cone_kernel<32, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                               nzb);
+    } else {
+        if (axial)
+            hipLaunchKernelGGL((bpT_cone_kernel<16, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                               nzb);
+        else
+            hipLaunchKernelGGL((bpT_cone_kernel<16, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+                               nzb);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace ph

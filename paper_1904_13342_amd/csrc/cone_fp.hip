@@ -24,7 +24,7 @@ constexpr int FP_TILE = 16;            // detector tile edge (pixels)
 constexpr int FP_D = 8;                // slab depth (planes along A)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
 constexpr int FP_LDS_FLOATS = 9984;    // 39 KiB slab capacity: four workgroups per CU
-constexpr int FP_BIAS = 4;             // keeps biased coordinates positive (floor == truncation)
+constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
 
 template <typename T>
 __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix, int iy, int iz)
@@ -100,9 +100,9 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
     const int NB = AX == 0 ? g.ny : g.nx, NC = g.nz;
     const float sgn = cr[0].e[AX] > 0.0f ? 1.0f : -1.0f;
     // biased coordinates of this ray
-    const float PA0 = r.p[AX] + (float)FP_BIAS, eA = r.e[AX];
-    const float PB0 = r.p[BX] + (float)FP_BIAS, eB = r.e[BX];
-    const float PC0 = r.p[2] + (float)FP_BIAS, eC = r.e[2];
+    const float PA0 = r.p[AX] + RAY_BIAS, eA = r.e[AX];
+    const float PB0 = r.p[BX] + RAY_BIAS, eB = r.e[BX];
+    const float PC0 = r.p[2] + RAY_BIAS, eC = r.e[2];
 
     // slabs cover floor(A) in [-2, NA]; slab s holds floor(A) in [-2 + s D, -2 + (s+1) D)
     if (tid == 0) {
@@ -270,10 +270,10 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
 
     float acc = 0.0f;
     if (!slab_ok) {
-        for (int m = kb; m <= ke; ++m) {
-            const float fm = (float)m;
-            acc += sample_global(f, g, fmaf(fm, r.e[0], r.p[0]), fmaf(fm, r.e[1], r.p[1]), fmaf(fm, r.e[2], r.p[2]));
-        }
+        const float P0 = r.p[0] + RAY_BIAS, P1 = r.p[1] + RAY_BIAS, P2 = r.p[2] + RAY_BIAS;
+        for (int m = kb; m <= ke; ++m)
+            acc += sample_global(f, g, ray_coord_biased(P0, r.e[0], m) - RAY_BIAS,
+                                 ray_coord_biased(P1, r.e[1], m) - RAY_BIAS, ray_coord_biased(P2, r.e[2], m) - RAY_BIAS);
     } else if (ax == 0) {
         acc = slab_walk<T, 0>(g, f, slab, s_range, r, cr, hit, kb, ke);
     } else {

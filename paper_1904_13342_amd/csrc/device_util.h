@@ -37,6 +37,18 @@ __device__ __forceinline__ Ray make_cone_ray(const Geom3D &g, const ConeFPView &
     return r;
 }
 
+// Sample positions of cone rays are evaluated around a +4 bias on every axis
+// (biased coordinates stay positive, so the slab walk can floor by
+// truncation); un-biasing is exact (subtracting 4 from a float in [4, 2^20)).
+// Every kernel that visits cone samples uses this one expression, so the
+// projector and its transpose see bitwise the same positions.
+constexpr float RAY_BIAS = 4.0f;
+
+__device__ __forceinline__ float ray_coord_biased(float p_biased, float e, int m)
+{
+    return fmaf((float)m, e, p_biased);
+}
+
 // Ray of 2D detector bin j in a view with central ray vector c: index
 // coordinates (x, y) of its anchor and of one step (fan rays set up in double
 // precision for the same reason as cone rays).
