@@ -293,9 +293,73 @@ def fbp(spec, p, W_red=None, K=None, W=None, slices=None):
     return backproject(spec, q, slices=slices)
 
 
+# ------------------------------------------------------- learned corrector
+#
+# Sec. III.A (trainable projection-domain weights in the FDK network of Eq. 5,
+# updated from a loss computed in the volume) and Sec. III.B / Eq. 6 (the
+# filter K as the trainable layer, initialised with the ramp):
+#     x = B q,  q = filter_K(r),  r = W * W_red * W_cos * p,
+# trained on the mean squared error to the ground-truth volume with Adam.
+
+def mse(x, ref, mask=None):
+    """L = mean((m (x - ref))^2) and dL/dx = 2 m^2 (x - ref) / n."""
+    x = np.asarray(x, dtype=np.float64)
+    d = x - np.asarray(ref, dtype=np.float64)
+    m = np.ones_like(d) if mask is None else np.asarray(mask, dtype=np.float64)
+    return float(np.mean((m * d) ** 2)), 2.0 * m * m * d / d.size
+
+
+def corrector_grad(spec, p, grad_q, K, W_red=None, W=None):
+    """(dL/dK, dL/dW) for q = filter_K(W W_red W_cos p), given g = dL/dq;
+    ``p`` and ``grad_q`` are [n_proj, nv, nu] or [batch, n_proj, nv, nu].
+
+    The filter output is Re IDFT_M(K . DFT_M(r)) on zero-padded rows, which
+    is linear in K:  q_n = (1/M) sum_f K[f] Re(R_f exp(2 pi i f n / M)).
+    Hence dL/dK[f] = (1/M) sum over rows and n < nu of g_n Re(R_f exp(...)),
+    which is (1/M) sum_rows Re(R_f conj(G_f)) with G = DFT_M(g) (g real) --
+    taken here with K's symmetric part, the one the real output depends on:
+    dL/dK[f] = (c[f] + c[M - f]) / 2.  The row filter is a circular
+    convolution with an even kernel restricted to the first nu samples, so it
+    is its own transpose: dL/dr = filter_K(g), and dL/dW[i][j] is the sum
+    over batch and views of dL/dr * W_red * W_cos * p."""
+    K = np.asarray(K, dtype=np.float64)
+    M = len(K)
+    shp = _proj_shape(spec)
+    p4 = np.asarray(p, dtype=np.float64).reshape((-1,) + shp)
+    g4 = np.asarray(grad_q, dtype=np.float64).reshape((-1,) + shp)
+    nv, nu = shp[1], shp[2]
+    c = np.zeros(M)
+    dW = np.zeros((nv, nu))
+    for b in range(p4.shape[0]):
+        r = weight(spec, p4[b], W_red=W_red, W=W)
+        R = np.fft.fft(r, n=M, axis=-1)
+        G = np.fft.fft(g4[b], n=M, axis=-1)
+        c += np.real(R * np.conj(G)).reshape(-1, M).sum(axis=0) / M
+        dr = circular_filter(g4[b], K)
+        dW += (dr * weight(spec, p4[b], W_red=W_red)).sum(axis=0)
+    mirror = c[(M - np.arange(M)) % M]
+    return 0.5 * (c + mirror), dW
+
+
+def corrector_forward(spec, p, K, W_red=None, W=None):
+    """x = B filter_K(W W_red W_cos p) for one set of projections."""
+    return fbp(spec, p, W_red=W_red, K=K, W=W)
+
+
+def adam(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, Algorithm 1) on float64 copies; returns
+    (param, m, v)."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return np.asarray(param, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
 __all__ = [
     "build", "geom", "num_threads", "project", "project_adjoint", "count_samples", "backproject",
     "backproject_adjoint", "tau", "fft_size", "ramlak_filter", "circular_filter", "ramlak_response",
     "ramp_response", "cosine_weights", "redundancy_weights", "parker", "projection_matrices", "weight",
-    "filter_projections", "fbp",
+    "filter_projections", "fbp", "mse", "corrector_grad", "corrector_forward", "adam",
 ]
