@@ -57,7 +57,8 @@ typedef enum {
     PH_ERR_DTYPE = -4,       /* unknown storage type */
     PH_ERR_WORKSPACE = -5,   /* workspace NULL or smaller than required */
     PH_ERR_HIP = -6,         /* a HIP call or kernel launch failed */
-    PH_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+    PH_ERR_UNSUPPORTED = -7, /* valid request this build does not implement */
+    PH_ERR_VALUE = -8        /* scalar argument non-finite or out of range */
 } ph_status;
 
 typedef enum { PH_F32 = 0, PH_F16 = 1, PH_BF16 = 2 } ph_dtype;
@@ -184,6 +185,16 @@ int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const v
  * M = 0 with K = NULL selects the default length. */
 int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
                         const float *W_red, int batch, int dtype, void *stream);
+
+/* Filter responses on the M-point DFT grid for the K argument above
+ * (Sec. II.C.4; Sec. III.B initialises the learned filter with the ramp).
+ * Host only.  kind 0: Ram-Lak, the DFT of the taps h(0) = 1/(4 tau^2),
+ * h(n odd) = -1/(n pi tau)^2, h(n even) = 0 for |n| <= M/2, times tau;
+ * kind 1: the ramp |f| sampled on the grid, K[k] = min(k, M-k) / (M tau).
+ * tau is the iso-centre sample spacing (du for parallel beams, du*SID/SDD
+ * for fan and cone beams).  K: host float[M]; M a power of two in [2, 4096],
+ * tau > 0 and finite. */
+int ph_filter_response(int kind, int M, double tau, float *K);
 int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M,
                         const float *W_red, const float *W, int batch, int dtype, void *stream);
 
@@ -201,6 +212,57 @@ int ph_fbp_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, vo
 int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
                   const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, int dtype,
                   void *stream);
+
+/* ------------------------------------------- learned corrector training
+ * The FDK network of Eq. 5 with trainable projection-domain parameters:
+ * Sec. III.A lets the redundancy weights be learned from a loss computed in
+ * the volume (the update follows Wurfl et al.), Sec. III.B / Eq. 6 trains the
+ * filter K, initialised with the ramp.  The corrected reconstruction is
+ *     x = B q,   q = F^H K F r,   r = W * W_red * W_cos * p
+ * (ph_weight_filter_3d then ph_backproject_cone3d, or ph_fdk_cone3d).  Its
+ * gradient runs backwards through the same operators: dL/dx from
+ * ph_mse_grad, dL/dq = B^T dL/dx from ph_backproject_adjoint_cone3d, then
+ * ph_corrector_grad_3d gives dL/dK and dL/dW, and ph_adam_step updates
+ * them.  All FP32. */
+
+/* L = (1/n) sum_i (m_i (x_i - ref_i))^2 and dL/dx_i = 2 m_i^2 (x_i - ref_i) / n
+ * (m_i = mask[i], or 1 when mask is NULL).
+ *   x, ref, grad : device float[n]; mask: device float[n] or NULL;
+ *   loss         : device double[1], overwritten: FP32 partial sums per
+ *                  workgroup, added in FP64 with atomics (the last bits may
+ *                  vary from run to run);
+ * n >= 1 (else PH_ERR_SHAPE).  grad may alias x, not ref. */
+int ph_mse_grad(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss,
+                void *stream);
+
+/* Gradients of L with respect to the filter K and the pixel weights W, given
+ * grad_q = dL/dq for q = Re IDFT_M(K_s . DFT_M(r)) row by row, with
+ * r = W * W_red * W_cos * proj and K_s[f] = (K[f] + K[(M - f) mod M]) / 2
+ * (the symmetrised response every filter call applies):
+ *   dL/dK[f]    = (1/2M) sum_rows Re(R_f conj(G_f) + R_{M-f} conj(G_{M-f})),
+ *   dL/dW[i][j] = sum_{b,k} (dL/dr)[b][k][i][j] * W_red[k][j] * W_cos(i,j) * proj[b][k][i][j],
+ *   dL/dr       = Re IDFT_M(K_s . DFT_M(grad_q))  (the filter's transpose),
+ * with R = DFT_M(r), G = DFT_M(grad_q) over zero-padded rows.
+ *   proj, grad_q : device float[batch][n_proj][nv][nu];
+ *   K            : device float[M] (required), M a power of two in
+ *                  [max(16, nu), 4096];
+ *   W_red        : device float[n_proj][nu] or NULL (the default of
+ *                  ph_weight_filter_3d); W: device float[nv][nu] or NULL (ones);
+ *   dK           : device float[M] output; dW: device float[nv][nu] output or
+ *                  NULL to skip it.
+ * Partial sums are combined with float atomics: the last bits may vary from
+ * run to run. */
+int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *grad_q, const float *K, int M,
+                         const float *W_red, const float *W, float *dK, float *dW, int batch, void *stream);
+
+/* One Adam step (Kingma & Ba) on n parameters, in place:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   param -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ *   param, m, v : device float[n], updated; grad : device float[n];
+ * t >= 1 is the step count (bias correction); lr > 0, b1 and b2 in [0, 1),
+ * eps > 0, all finite (else PH_ERR_VALUE); n >= 1 (else PH_ERR_SHAPE). */
+int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, float lr, float beta1,
+                 float beta2, float eps, int t, void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,5 +11,6 @@ _load_lib()
 from .ops import *  # noqa: E402,F401,F403
 from .ops import __all__ as _ops_all  # noqa: E402
 from . import autograd  # noqa: E402,F401
+from .corrector import LearnedCorrector  # noqa: E402,F401
 
-__all__ = list(_ops_all) + ["autograd"]
+__all__ = list(_ops_all) + ["autograd", "LearnedCorrector"]

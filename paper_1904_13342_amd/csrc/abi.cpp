@@ -345,26 +345,26 @@ double ramlak_tap(long n, double tau)
     return -1.0 / ((double)n * (double)n * kPi * kPi * tau * tau);
 }
 
+std::vector<float> ramlak_response(int M, double tau)
+{
+    std::vector<float> K((size_t)M);
+    for (int k = 0; k < M; ++k) {
+        double acc = ramlak_tap(0, tau);
+        for (int n = 1; n < M; n += 2) {  // odd taps only; even taps are zero
+            const long nn = n <= M / 2 ? n : n - M;
+            acc += ramlak_tap(nn, tau) * std::cos(2.0 * kPi * (double)(((long)k * n) % M) / M);
+        }
+        K[(size_t)k] = (float)(tau * acc);
+    }
+    return K;
+}
+
 const float *ramlak_table(int M, double tau, int *st)
 {
     std::string key = "ramlak";
     append(key, &M, 1);
     append(key, &tau, 1);
-    return (const float *)cached(
-        key,
-        [&] {
-            std::vector<float> K((size_t)M);
-            for (int k = 0; k < M; ++k) {
-                double acc = ramlak_tap(0, tau);
-                for (int n = 1; n < M; n += 2) {  // odd taps only; even taps are zero
-                    const long nn = n <= M / 2 ? n : n - M;
-                    acc += ramlak_tap(nn, tau) * std::cos(2.0 * kPi * (double)(((long)k * n) % M) / M);
-                }
-                K[(size_t)k] = (float)(tau * acc);
-            }
-            return as_bytes(K);
-        },
-        st);
+    return (const float *)cached(key, [&] { return as_bytes(ramlak_response(M, tau)); }, st);
 }
 
 const float2 *twiddle_table(int M, int *st)
@@ -687,6 +687,7 @@ const char *ph_status_string(int s)
     case PH_ERR_WORKSPACE: return "workspace missing or too small";
     case PH_ERR_HIP: return "HIP runtime error";
     case PH_ERR_UNSUPPORTED: return "unsupported request";
+    case PH_ERR_VALUE: return "scalar argument non-finite or out of range";
     default: return "unknown status";
     }
 }
@@ -970,6 +971,70 @@ int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const v
         return st;
     return to_status(launch_backproject_adjoint_cone(G, (const ConeBPView *)views, axial, bp_segment(g),
                                                      (const float *)vol, (float *)proj, batch, (hipStream_t)stream));
+}
+
+int ph_filter_response(int kind, int M, double tau, float *K)
+{
+    if (!K)
+        return PH_ERR_NULL;
+    if (!is_pow2(M) || M < 2 || M > 4096)
+        return PH_ERR_SHAPE;
+    if (!finite_pos(tau) || (kind != 0 && kind != 1))
+        return PH_ERR_VALUE;
+    if (kind == 1) {
+        for (int k = 0; k < M; ++k)
+            K[k] = (float)((double)(k <= M / 2 ? k : M - k) / ((double)M * tau));
+        return PH_OK;
+    }
+    const std::vector<float> t = ramlak_response(M, tau);
+    std::memcpy(K, t.data(), sizeof(float) * (size_t)M);
+    return PH_OK;
+}
+
+int ph_mse_grad(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss, void *stream)
+{
+    if (!x || !ref || !grad || !loss)
+        return PH_ERR_NULL;
+    if (n < 1)
+        return PH_ERR_SHAPE;
+    return to_status(launch_mse(x, ref, mask, n, grad, loss, (hipStream_t)stream));
+}
+
+int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *grad_q, const float *K, int M,
+                         const float *W_red, const float *W, float *dK, float *dW, int batch, void *stream)
+{
+    if (!proj || !grad_q || !K || !dK)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    Geom3D G;
+    int st = make_geom3d(g, &G);
+    if (st != PH_OK)
+        return st;
+    st = filter_len(K, M, g->det_shape[1], &M);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(2, g->det_shape[1], g->det_shape[0], g->n_proj, batch, g->det_spacing[1], g->det_spacing[0],
+                     g->sid, g->sdd, g->angular_range, K, M, W_red, W, &a);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_corrector_grad(a, proj, grad_q, dK, dW, (hipStream_t)stream));
+}
+
+int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, float lr, float beta1, float beta2,
+                 float eps, int t, void *stream)
+{
+    if (!param || !grad || !m || !v)
+        return PH_ERR_NULL;
+    if (n < 1)
+        return PH_ERR_SHAPE;
+    const bool ok = std::isfinite(lr) && lr > 0.0f && std::isfinite(beta1) && beta1 >= 0.0f && beta1 < 1.0f &&
+                    std::isfinite(beta2) && beta2 >= 0.0f && beta2 < 1.0f && std::isfinite(eps) && eps > 0.0f &&
+                    t >= 1;
+    if (!ok)
+        return PH_ERR_VALUE;
+    return to_status(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
 }
 
 }  // extern "C"

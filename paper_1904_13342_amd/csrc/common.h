@@ -120,4 +120,12 @@ struct FilterArgs {
 };
 hipError_t launch_weight_filter(int dtype, const FilterArgs &a, const void *in, float *out, hipStream_t stream);
 
+// Learned-corrector training (FP32)
+hipError_t launch_mse(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss,
+                      hipStream_t stream);
+hipError_t launch_corrector_grad(const FilterArgs &a, const float *proj, const float *grad_q, float *dK, float *dW,
+                                 hipStream_t stream);
+hipError_t launch_adam(float *param, const float *grad, float *m, float *v, size_t n, float lr, float b1, float b2,
+                       float eps, int t, hipStream_t stream);
+
 }  // namespace ph

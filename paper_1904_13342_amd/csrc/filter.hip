@@ -10,145 +10,12 @@
 // radix-8 passes (radix 4 or 2 for the last one) in LDS with the butterflies
 // in registers, natural order in and out.  Workgroups loop over row pairs
 // (grid sized to the machine) with the twiddle half-table held in LDS.
-#include "common.h"
+#include "fft.h"
 
 namespace ph {
 namespace {
 
-constexpr int WF_THREADS = 256;
-
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b)
-{
-    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
-
-// a * exp(DIR * 2 pi i * k / R) for a compile-time k (DIR = -1 forward, +1 inverse)
-template <int R, int K, int DIR>
-__device__ __forceinline__ float2 rot(float2 a)
-{
-    constexpr int k = ((K % R) + R) % R;
-    if constexpr (k == 0) {
-        return a;
-    } else if constexpr (4 * k == R) {   // exp(DIR i pi/2) = DIR * i
-        return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
-    } else if constexpr (2 * k == R) {   // -1
-        return make_float2(-a.x, -a.y);
-    } else if constexpr (4 * k == 3 * R) {   // exp(DIR i 3pi/2) = -DIR * i
-        return DIR < 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
-    } else {
-        static_assert(R == 8 && (k == 1 || k == 3), "odd multiples of pi/4 only");
-        constexpr float h = 0.70710678118654752440f;   // cos(pi/4) = sin(pi/4)
-        return cmul(a, make_float2(k == 1 ? h : -h, DIR * h));
-    }
-}
-
-// In-register DFT of size R (2, 4 or 8): decimation in frequency, then the
-// bit-reversal permutation, so v[k] = sum_n v[n] exp(DIR 2 pi i n k / R).
-template <int R, int DIR>
-__device__ __forceinline__ void dft(float2 *v)
-{
-#pragma unroll
-    for (int h = R / 2; h >= 1; h >>= 1) {
-#pragma unroll
-        for (int g0 = 0; g0 < R; g0 += 2 * h) {
-#pragma unroll
-            for (int t = 0; t < h; ++t) {
-                const float2 a = v[g0 + t], b = v[g0 + t + h];
-                v[g0 + t] = cadd(a, b);
-                const float2 d = csub(a, b);
-                // twiddle exp(DIR 2 pi i t / (2h)) = exp(DIR 2 pi i t (R / 2h) / R)
-                switch (t * (R / (2 * h))) {
-                case 0: v[g0 + t + h] = d; break;
-                case 1: v[g0 + t + h] = rot<R, 1, DIR>(d); break;
-                case 2: v[g0 + t + h] = rot<R, 2, DIR>(d); break;
-                case 3: v[g0 + t + h] = rot<R, 3, DIR>(d); break;
-                default: break;
-                }
-            }
-        }
-    }
-    if constexpr (R == 4) {
-        const float2 t1 = v[1];
-        v[1] = v[2];
-        v[2] = t1;
-    } else if constexpr (R == 8) {
-        float2 t1 = v[1];
-        v[1] = v[4];
-        v[4] = t1;
-        t1 = v[3];
-        v[3] = v[6];
-        v[6] = t1;
-    }
-}
-
-// One in-place Stockham pass of radix R over M points with span Ns (the
-// product of the radices of the previous passes): every item's inputs are
-// read into registers, then all outputs are written.  At most MAXIT items per
-// thread (M <= 4096).  Twiddles come from the LDS half table
-// tw[t] = exp(-2 pi i t / M), t < M/2, with exp(-2 pi i (t + M/2) / M) = -tw[t].
-template <int R, int DIR>
-__device__ __forceinline__ void stockham_pass(float2 *buf, const float2 *tw, int M, int Ns)
-{
-    constexpr int MAXIT = 4096 / R / WF_THREADS;
-    const int items = M / R;
-    const int twscale = M / (Ns * R);
-    const int half = M >> 1;
-    float2 v[MAXIT][R];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        const int j = threadIdx.x + it * WF_THREADS;
-        if (j < items) {
-            const int jm = j & (Ns - 1);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float2 x = buf[j + r * items];
-                if (r > 0 && jm > 0) {
-                    const int t = (jm * r * twscale) & (M - 1);
-                    float2 w = tw[t & (half - 1)];
-                    if (t >= half)
-                        w = make_float2(-w.x, -w.y);
-                    if (DIR > 0)
-                        w.y = -w.y;
-                    x = cmul(x, w);
-                }
-                v[it][r] = x;
-            }
-            dft<R, DIR>(v[it]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        const int j = threadIdx.x + it * WF_THREADS;
-        if (j < items) {
-            const int jm = j & (Ns - 1);
-            const int base = (j - jm) * R + jm;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                buf[base + r * Ns] = v[it][r];
-        }
-    }
-    __syncthreads();
-}
-
-// Full in-place transform of buf (natural order in and out).
-template <int DIR>
-__device__ __forceinline__ void fft(float2 *buf, const float2 *tw, int M, int log2M)
-{
-    int Ns = 1;
-    int left = log2M;
-    while (left >= 3) {
-        stockham_pass<8, DIR>(buf, tw, M, Ns);
-        Ns *= 8;
-        left -= 3;
-    }
-    if (left == 2)
-        stockham_pass<4, DIR>(buf, tw, M, Ns);
-    else if (left == 1)
-        stockham_pass<2, DIR>(buf, tw, M, Ns);
-}
+using namespace lds_fft;
 
 template <typename T>
 __device__ __forceinline__ float weighted(const FilterArgs &a, const T *in, long row, int j)
@@ -192,7 +59,7 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
             buf[n] = z;
         }
         __syncthreads();
-        fft<-1>(buf, tw, M, a.log2M);
+        transform<-1>(buf, tw, M, a.log2M);
         // multiply by the symmetrised real response
         for (int n = tid; n < M; n += WF_THREADS) {
             const float kf = 0.5f * (a.K[n] + a.K[(M - n) & (M - 1)]);
@@ -200,7 +67,7 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
             buf[n].y *= kf;
         }
         __syncthreads();
-        fft<1>(buf, tw, M, a.log2M);
+        transform<1>(buf, tw, M, a.log2M);
         for (int n = tid; n < a.nu; n += WF_THREADS) {
             const float2 z = buf[n];
             out[(size_t)ra * a.nu + n] = z.x * inv;

@@ -243,6 +243,79 @@ def weight_filter_3d(g, proj, K=None, M=None, W_red=None, W=None, out=None):
     return out
 
 
+def filter_response(kind, M, tau):
+    """Host float32 [M] response on the M-point grid: kind "ramlak" or "ramp"."""
+    kinds = {"ramlak": 0, "ramp": 1}
+    if kind not in kinds:
+        raise ValueError(f"kind must be one of {sorted(kinds)}")
+    K = (ctypes.c_float * int(M))()
+    check("ph_filter_response", lib().ph_filter_response(kinds[kind], int(M), float(tau), K))
+    return torch.tensor(list(K), dtype=torch.float32)
+
+
+def _f32_like(t, name, numel=None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mse_grad(x, ref, mask=None, grad=None, loss=None):
+    """(loss, grad): L = mean((mask * (x - ref))^2) as a float64 device scalar, and dL/dx."""
+    n = x.numel()
+    px = _f32_like(x, "x")
+    pr = _f32_like(ref, "ref", n)
+    pm = None if mask is None else _f32_like(mask, "mask", n)
+    if grad is None:
+        grad = torch.empty_like(x)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float64, device=x.device)
+    if loss.dtype != torch.float64 or loss.numel() != 1 or loss.device != x.device:
+        raise ValueError("loss must be a one-element float64 tensor on the device of x")
+    status = lib().ph_mse_grad(px, pr, pm, n, _f32_like(grad, "grad", n), ctypes.c_void_p(loss.data_ptr()),
+                               _stream(x))
+    check("ph_mse_grad", status)
+    return loss, grad
+
+
+def corrector_grad_3d(g, proj, grad_q, K, W_red=None, W=None, dK=None, dW=None, want_dW=True):
+    """(dL/dK, dL/dW) of q = F^H K F (W W_red W_cos proj) given dL/dq; dW is
+    None when want_dW is false."""
+    if proj.dtype != torch.float32 or grad_q.dtype != torch.float32:
+        raise ValueError("proj and grad_q must be float32")
+    batch = _dev(proj, "proj", _sino_tail(g))
+    if _dev(grad_q, "grad_q", _sino_tail(g)) != batch or grad_q.shape != proj.shape:
+        raise ValueError("grad_q must have the shape of proj")
+    M = K.numel()
+    nv, nu = g.det_shape[0], g.det_shape[1]
+    if dK is None:
+        dK = torch.empty(M, dtype=torch.float32, device=proj.device)
+    if want_dW and dW is None:
+        dW = torch.empty((nv, nu), dtype=torch.float32, device=proj.device)
+    if not want_dW:
+        dW = None
+    status = lib().ph_corrector_grad_3d(ctypes.byref(g), ctypes.c_void_p(proj.data_ptr()),
+                                        ctypes.c_void_p(grad_q.data_ptr()), _f32_like(K, "K"), M,
+                                        _f32_dev(W_red, "W_red", g.n_proj * nu), _f32_dev(W, "W", nv * nu),
+                                        _f32_like(dK, "dK", M), None if dW is None else _f32_like(dW, "dW", nv * nu),
+                                        batch, _stream(proj))
+    check("ph_corrector_grad_3d", status)
+    return dK, dW
+
+
+def adam_step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One in-place Adam step (t counts from 1)."""
+    n = param.numel()
+    status = lib().ph_adam_step(_f32_like(param, "param"), _f32_like(grad, "grad", n), _f32_like(m, "m", n),
+                                _f32_like(v, "v", n), n, float(lr), float(beta1), float(beta2), float(eps), int(t),
+                                _stream(param))
+    check("ph_adam_step", status)
+    return param
+
+
 def workspace_bytes_2d(g, batch=1):
     return int(lib().ph_workspace_bytes_2d(ctypes.byref(g), int(batch)))
 
@@ -307,5 +380,5 @@ __all__ = [
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "version",
+    "fbp_fan2d", "fdk_cone3d", "filter_response", "mse_grad", "corrector_grad_3d", "adam_step", "version",
 ]

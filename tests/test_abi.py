@@ -54,7 +54,7 @@ def test_binding_covers_every_symbol(ph):
 
 def test_status_strings(L):
     assert L.ph_status_string(0) == b"ok"
-    for s in range(-7, 0):
+    for s in range(-8, 0):
         assert L.ph_status_string(s) not in (b"ok", b"unknown status")
     assert b"gfx950" in L.ph_version()
 
@@ -179,6 +179,46 @@ def test_rejects_bad_filter_length_and_workspace(ph, L):
         assert st == -2, M
     # the default Ram-Lak length must avoid wrap-around
     assert L.ph_weight_filter_3d(ctypes.byref(g), FAKE, FAKE, None, 64, None, None, 1, 0, None) == -2
+
+
+def test_rejects_bad_corrector_arguments(ph, L):
+    g = _good3(ph)
+    G = ctypes.byref(g)
+    # MSE: null pointers and n = 0
+    assert L.ph_mse_grad(None, FAKE, None, 10, FAKE, FAKE, None) == -1
+    assert L.ph_mse_grad(FAKE, FAKE, None, 10, FAKE, None, None) == -1
+    assert L.ph_mse_grad(FAKE, FAKE, None, 0, FAKE, FAKE, None) == -2
+    # corrector gradient: K is required, lengths as for the filter, geometry checked
+    assert L.ph_corrector_grad_3d(G, FAKE, FAKE, None, 64, None, None, FAKE, FAKE, 1, None) == -1
+    assert L.ph_corrector_grad_3d(G, FAKE, FAKE, FAKE, 64, None, None, None, FAKE, 1, None) == -1
+    assert L.ph_corrector_grad_3d(G, FAKE, FAKE, FAKE, 64, None, None, FAKE, FAKE, 0, None) == -2
+    for M in (100, 32, 8192):
+        assert L.ph_corrector_grad_3d(G, FAKE, FAKE, FAKE, M, None, None, FAKE, FAKE, 1, None) == -2
+    bad = _good3(ph)
+    bad.sdd = bad.sid
+    assert L.ph_corrector_grad_3d(ctypes.byref(bad), FAKE, FAKE, FAKE, 64, None, None, FAKE, FAKE, 1, None) == -3
+    # Adam: hyper-parameters
+    ok = dict(lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, t=1)
+    assert L.ph_adam_step(FAKE, FAKE, None, FAKE, 5, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
+    assert L.ph_adam_step(FAKE, FAKE, FAKE, FAKE, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -2
+    for key, value in [("lr", 0.0), ("lr", float("nan")), ("b1", 1.0), ("b2", -0.1), ("eps", 0.0), ("t", 0)]:
+        a = dict(ok, **{key: value})
+        st = L.ph_adam_step(FAKE, FAKE, FAKE, FAKE, 5, a["lr"], a["b1"], a["b2"], a["eps"], a["t"], None)
+        assert st == -8, key
+
+
+def test_filter_response_matches_oracle(L, ora):
+    for kind, ref_fn in ((0, ora.ramlak_response), (1, ora.ramp_response)):
+        for M in (16, 1024):
+            K = (ctypes.c_float * M)()
+            assert L.ph_filter_response(kind, M, 0.625, K) == 0
+            ref = ref_fn(M, 0.625)
+            assert np.abs(np.array(K) - ref).max() <= 1e-7 * np.abs(ref).max()
+    K = (ctypes.c_float * 16)()
+    assert L.ph_filter_response(0, 16, 0.625, None) == -1
+    assert L.ph_filter_response(0, 24, 0.625, K) == -2
+    assert L.ph_filter_response(2, 16, 0.625, K) == -8
+    assert L.ph_filter_response(1, 16, -1.0, K) == -8
 
 
 def test_binding_checks_tensor_shapes(ph):
