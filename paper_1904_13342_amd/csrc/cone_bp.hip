@@ -51,6 +51,64 @@ __device__ __forceinline__ float bilerp_global(const TI *q, const Geom3D &g, flo
     return fmaf(fv, a1 - a0, a0);
 }
 
+// Footprint of a brick on the detector for one view: the projections of its
+// 8 corners (one per lane, lane mod 8) reduced across lanes, widened by one
+// pixel.  B and B^T call this with the same corners, so they stage the same
+// tile and evaluate the same tile-local coordinates.
+struct Footprint {
+    int u_lo, v_lo, tw, th;
+};
+
+__device__ __forceinline__ Footprint brick_footprint(const ConeBPView &v, const Geom3D &g, float cx, float cy,
+                                                     float cz)
+{
+#pragma clang fp contract(off)
+    const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
+    const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
+    const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
+    Footprint f;
+    f.u_lo = (int)floorf(umin + g.cu) - 1;
+    f.v_lo = (int)floorf(vmin + g.cv) - 1;
+    f.tw = (int)floorf(umax + g.cu) + 2 - f.u_lo + 1;
+    f.th = (int)floorf(vmax + g.cv) + 2 - f.v_lo + 1;
+    return f;
+}
+
+// Per-column quantities of a circular view (the matrices have no z term in
+// the u and w rows): distance weight (SID/w)^2, centred detector coordinates
+// (uc, vc0) of the column's first voxel and the row step per voxel in z.
+// Shared by B and B^T (no contraction across these roundings), so the pair
+// sees bitwise the same positions.
+struct AxialCol {
+    float wt, uc, vc0, dvz;
+};
+
+__device__ __forceinline__ AxialCol axial_col(const ConeBPView &v, float sid, float xc, float yc, float zc0)
+{
+#pragma clang fp contract(off)
+    AxialCol c;
+    const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc0));
+    const float sw = sid * rW;
+    c.wt = sw * sw;
+    c.uc = dot4(v.r[0], xc, yc, zc0) * rW;
+    c.vc0 = dot4(v.r[1], xc, yc, zc0) * rW;
+    c.dvz = v.r[1][2] * rW;
+    return c;
+}
+
+// detector coordinate relative to a staged tile (lo) or absolute (lo = 0 form)
+__device__ __forceinline__ float tile_coord(float c, float centre, int lo)
+{
+#pragma clang fp contract(off)
+    return c + centre - (float)lo;
+}
+
+__device__ __forceinline__ float det_coord(float c, float centre)
+{
+#pragma clang fp contract(off)
+    return c + centre;
+}
+
 template <typename T, typename TI, int BP_NZ, bool AXIAL>
 __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
                                                       const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
@@ -85,13 +143,8 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
 
     for (int k = 0; k < g.n_proj; ++k) {
         const ConeBPView v = views[k];
-        // footprint of the brick on the detector
-        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
-        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
-        const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
-        const int u_lo = (int)floorf(umin + g.cu) - 1, u_hi = (int)floorf(umax + g.cu) + 2;
-        const int v_lo = (int)floorf(vmin + g.cv) - 1, v_hi = (int)floorf(vmax + g.cv) + 2;
-        const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
+        const Footprint fp = brick_footprint(v, g, cx, cy, cz);
+        const int u_lo = fp.u_lo, v_lo = fp.v_lo, tw = fp.tw, th = fp.th;
         const bool staged = tw <= BP_TW && th <= BP_TH;
         const TI *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged) {
@@ -110,15 +163,12 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
         if (!active)
             continue;
         if (AXIAL) {
-            const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc0));
-            const float sw = g.sid * rW, wt = sw * sw;
-            const float uc = dot4(v.r[0], xc, yc, zc0) * rW;
-            const float vc0 = dot4(v.r[1], xc, yc, zc0) * rW;
-            const float dvz = v.r[1][2] * rW;
+            const AxialCol ac = axial_col(v, g.sid, xc, yc, zc0);
+            const float wt = ac.wt, dvz = ac.dvz;
             if (staged) {
                 // tile-local coordinates are >= 1 (one-pixel margin): floor == truncation
-                const float su = uc + g.cu - (float)u_lo;
-                const float sv0 = vc0 + g.cv - (float)v_lo;
+                const float su = tile_coord(ac.uc, g.cu, u_lo);
+                const float sv0 = tile_coord(ac.vc0, g.cv, v_lo);
                 const int iu = (int)su;
                 const float fu = __builtin_amdgcn_fractf(su);
                 const float *col = tile + iu;
@@ -141,7 +191,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                     }
                 }
             } else {
-                const float su = uc + g.cu, sv0 = vc0 + g.cv;
+                const float su = det_coord(ac.uc, g.cu), sv0 = det_coord(ac.vc0, g.cv);
 #pragma unroll
                 for (int z = 0; z < BP_NZ; ++z)
                     if (z < zcount)
@@ -183,16 +233,30 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
 // detector coordinates (so the pair is transposed to the last rounding of the
 // positions), with each voxel's value times dbeta * (SID/w)^2 splatted into
 // the four pixels of its bilinear footprint.  Splats go to an LDS tile of the
-// brick's footprint (LDS atomics); the tile is then added to the projections
-// with one global float atomic per pixel.  FP32 in and out; the output must be
-// zero on entry.
+// brick's footprint; the tile is then added to the projections with one global
+// float atomic per pixel.  FP32 in and out; the output must be zero on entry.
+//
+// The LDS tile accumulates in FP64: on gfx950 an FP64 LDS atomic add to
+// distinct addresses runs about twenty times faster than an FP32 one, which
+// the hardware serialises, and the sums come out more accurate besides.
+// Equal addresses within one instruction still serialise, and columns lined
+// up along a ray land on the same detector column, so for circular views the
+// lanes of a wave are laid out across the rays: 16 columns on a line along
+// the volume axis most perpendicular to the view's central ray times 4 groups
+// of z (a quarter of the segment apart), and each thread's voxels (4 columns
+// x NZ/4 z) are re-read whenever the views' orientation changes.  One
+// instruction then hits 64 distinct pixels whenever neighbouring columns
+// project at least a pixel apart.
 
-__device__ __forceinline__ void splat_tile(float *p, float x, float fu, float fv)
+constexpr int BPT_TS = BP_TW + 1;   // tile row stride (FP64 cells): rows start in different banks
+
+__device__ __forceinline__ void splat_tile(double *p, float x, float fu, float fv, int stride)
 {
-    atomicAdd(p, x * (1.0f - fu) * (1.0f - fv));
-    atomicAdd(p + 1, x * fu * (1.0f - fv));
-    atomicAdd(p + BP_TW, x * (1.0f - fu) * fv);
-    atomicAdd(p + BP_TW + 1, x * fu * fv);
+    const float a = x * (1.0f - fv), b = x * fv;
+    atomicAdd(p, (double)(a * (1.0f - fu)));
+    atomicAdd(p + 1, (double)(a * fu));
+    atomicAdd(p + stride, (double)(b * (1.0f - fu)));
+    atomicAdd(p + stride + 1, (double)(b * fu));
 }
 
 __device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su, float sv, float x)
@@ -200,22 +264,145 @@ __device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su
     const float fsu = floorf(su), fsv = floorf(sv);
     const int j = (int)fsu, i = (int)fsv;
     const float fu = su - fsu, fv = sv - fsv;
-    if ((unsigned)i < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
-        unsafeAtomicAdd(q + (size_t)i * g.nu + j, x * (1.0f - fu) * (1.0f - fv));
-    if ((unsigned)i < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
-        unsafeAtomicAdd(q + (size_t)i * g.nu + j + 1, x * fu * (1.0f - fv));
-    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)j < (unsigned)g.nu)
-        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j, x * (1.0f - fu) * fv);
-    if ((unsigned)(i + 1) < (unsigned)g.nv && (unsigned)(j + 1) < (unsigned)g.nu)
-        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j + 1, x * fu * fv);
+    const float a = x * (1.0f - fv), b = x * fv;
+    const bool r0 = (unsigned)i < (unsigned)g.nv, r1 = (unsigned)(i + 1) < (unsigned)g.nv;
+    const bool c0 = (unsigned)j < (unsigned)g.nu, c1 = (unsigned)(j + 1) < (unsigned)g.nu;
+    if (r0 && c0)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j, a * (1.0f - fu));
+    if (r0 && c1)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j + 1, a * fu);
+    if (r1 && c0)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j, b * (1.0f - fu));
+    if (r1 && c1)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j + 1, b * fu);
 }
 
-template <int BP_NZ, bool AXIAL>
-__global__ void __launch_bounds__(256) bpT_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
-                                                       const float *__restrict__ vol, float *__restrict__ proj,
-                                                       int nbx, int nby, int nzb)
+__device__ __forceinline__ void zero_tile(double *tile, const Footprint &fp, int tid)
 {
-    __shared__ float tile[BP_TH * BP_TW];
+    for (int r = tid >> 4; r < fp.th; r += 16)
+        for (int c = tid & 15; c < fp.tw; c += 16)
+            tile[r * BPT_TS + c] = 0.0;
+}
+
+__device__ __forceinline__ void flush_tile(const double *tile, const Footprint &fp, const Geom3D &g, float *qk,
+                                           int tid)
+{
+    for (int r = tid >> 4; r < fp.th; r += 16) {
+        const int gi = fp.v_lo + r;
+        if ((unsigned)gi >= (unsigned)g.nv)
+            continue;
+        for (int c = tid & 15; c < fp.tw; c += 16) {
+            const int gj = fp.u_lo + c;
+            const float t = (float)tile[r * BPT_TS + c];
+            if (t != 0.0f && (unsigned)gj < (unsigned)g.nu)
+                unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
+        }
+    }
+}
+
+template <int BP_NZ>
+__global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                        const float *__restrict__ vol, float *__restrict__ proj,
+                                                        int nbx, int nby, int nzb)
+{
+    constexpr int ZQ = BP_NZ / 4;   // voxels in z per lane group
+    __shared__ double tile[BP_TH * BPT_TS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int a = lane & 15, zq = lane >> 4;
+    const unsigned lin = blockIdx.x;
+    const int bxi = (int)(lin % (unsigned)nbx), byi = (int)((lin / (unsigned)nbx) % (unsigned)nby);
+    const int bzb = (int)(lin / (unsigned)(nbx * nby));
+    const int zb = bzb % nzb, b = bzb / nzb;
+    const int z0 = zb * BP_NZ;
+    const int zcount = min(BP_NZ, g.nz - z0);
+
+    const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
+    const float zc0 = (float)z0 - hz;
+    const int corner = tid & 7;
+    const float cx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) : bxi * 16) - hx;
+    const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
+    const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
+
+    const float *vb = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)z0 * g.ny * g.nx;
+    float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
+    float val[4][ZQ];
+    int cur = -1;   // lane layout of val: 0 = lanes along y, 1 = lanes along x
+
+    for (int k = 0; k < g.n_proj; ++k) {
+        const ConeBPView v = views[k];
+        // rays mostly along x (depth row dominated by x): put the lanes along y
+        const int orient = fabsf(v.r[2][0]) >= fabsf(v.r[2][1]) ? 0 : 1;
+        if (orient != cur) {
+            cur = orient;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int ix = bxi * 16 + (orient == 0 ? 4 * wave + c : a);
+                const int iy = byi * 16 + (orient == 0 ? a : 4 * wave + c);
+                const bool act = ix < g.nx && iy < g.ny;
+                const float *src = vb + (size_t)(act ? iy : 0) * g.nx + (act ? ix : 0);
+#pragma unroll
+                for (int m = 0; m < ZQ; ++m) {
+                    const int z = zq * ZQ + m;
+                    val[c][m] = (act && z < zcount) ? g.dbeta * src[(size_t)z * g.ny * g.nx] : 0.0f;
+                }
+            }
+        }
+        const Footprint fp = brick_footprint(v, g, cx, cy, cz);
+        const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
+        float *qk = pb + (size_t)k * g.nv * g.nu;
+        if (staged) {
+            __syncthreads();   // the previous tile has been flushed
+            zero_tile(tile, fp, tid);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int ix = bxi * 16 + (orient == 0 ? 4 * wave + c : a);
+            const int iy = byi * 16 + (orient == 0 ? a : 4 * wave + c);
+            if (ix >= g.nx || iy >= g.ny)
+                continue;
+            const AxialCol ac = axial_col(v, g.sid, (float)ix - hx, (float)iy - hy, zc0);
+            const float wt = ac.wt, dvz = ac.dvz;
+            if (staged) {
+                const float su = tile_coord(ac.uc, g.cu, fp.u_lo);
+                const float sv0 = tile_coord(ac.vc0, g.cv, fp.v_lo);
+                const int iu = (int)su;
+                const float fu = __builtin_amdgcn_fractf(su);
+                double *col = tile + iu;
+#pragma unroll
+                for (int m = 0; m < ZQ; ++m) {
+                    const int z = zq * ZQ + m;
+                    if (z < zcount) {
+                        const float sv = fmaf((float)z, dvz, sv0);
+                        const int iv = (int)sv;
+                        splat_tile(col + iv * BPT_TS, wt * val[c][m], fu, __builtin_amdgcn_fractf(sv), BPT_TS);
+                    }
+                }
+            } else {
+                const float su = det_coord(ac.uc, g.cu), sv0 = det_coord(ac.vc0, g.cv);
+#pragma unroll
+                for (int m = 0; m < ZQ; ++m) {
+                    const int z = zq * ZQ + m;
+                    if (z < zcount)
+                        splat_global(qk, g, su, fmaf((float)z, dvz, sv0), wt * val[c][m]);
+                }
+            }
+        }
+        if (staged) {
+            __syncthreads();
+            flush_tile(tile, fp, g, qk, tid);
+        }
+    }
+}
+
+// General projection matrices: one thread per column segment, as in B.
+template <int BP_NZ>
+__global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                          const float *__restrict__ vol, float *__restrict__ proj,
+                                                          int nbx, int nby, int nzb)
+{
+    __shared__ double tile[BP_TH * BPT_TS];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
     const unsigned lin = blockIdx.x;
@@ -244,83 +431,37 @@ __global__ void __launch_bounds__(256) bpT_cone_kernel(Geom3D g, const ConeBPVie
 
     for (int k = 0; k < g.n_proj; ++k) {
         const ConeBPView v = views[k];
-        const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
-        const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
-        const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
-        const int u_lo = (int)floorf(umin + g.cu) - 1, u_hi = (int)floorf(umax + g.cu) + 2;
-        const int v_lo = (int)floorf(vmin + g.cv) - 1, v_hi = (int)floorf(vmax + g.cv) + 2;
-        const int tw = u_hi - u_lo + 1, th = v_hi - v_lo + 1;
-        const bool staged = tw <= BP_TW && th <= BP_TH;
+        const Footprint fp = brick_footprint(v, g, cx, cy, cz);
+        const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
         float *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged) {
-            __syncthreads();   // the previous tile has been flushed
-            for (int r = ty; r < th; r += 16)
-                for (int c = tx; c < tw; c += 16)
-                    tile[r * BP_TW + c] = 0.0f;
+            __syncthreads();
+            zero_tile(tile, fp, tid);
             __syncthreads();
         }
         if (active) {
-            if (AXIAL) {
-                const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc0));
-                const float sw = g.sid * rW, wt = sw * sw;
-                const float uc = dot4(v.r[0], xc, yc, zc0) * rW;
-                const float vc0 = dot4(v.r[1], xc, yc, zc0) * rW;
-                const float dvz = v.r[1][2] * rW;
-                if (staged) {
-                    const float su = uc + g.cu - (float)u_lo;
-                    const float sv0 = vc0 + g.cv - (float)v_lo;
-                    const int iu = (int)su;
-                    const float fu = __builtin_amdgcn_fractf(su);
-                    float *col = tile + iu;
 #pragma unroll
-                    for (int z = 0; z < BP_NZ; ++z) {
-                        if (z < zcount) {
-                            const float sv = fmaf((float)z, dvz, sv0);
-                            const int iv = (int)sv;
-                            splat_tile(col + iv * BP_TW, wt * val[z], fu, __builtin_amdgcn_fractf(sv));
-                        }
-                    }
-                } else {
-                    const float su = uc + g.cu, sv0 = vc0 + g.cv;
-#pragma unroll
-                    for (int z = 0; z < BP_NZ; ++z)
-                        if (z < zcount)
-                            splat_global(qk, g, su, fmaf((float)z, dvz, sv0), wt * val[z]);
-                }
-            } else {
-#pragma unroll
-                for (int z = 0; z < BP_NZ; ++z) {
-                    if (z < zcount) {
-                        const float zc = zc0 + (float)z;
-                        const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
-                        const float sw = g.sid * rW, wt = sw * sw;
-                        const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
-                        const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
-                        if (staged) {
-                            const float lu = su - (float)u_lo, lv = sv - (float)v_lo;
-                            const int iu = (int)lu, iv = (int)lv;
-                            splat_tile(tile + iv * BP_TW + iu, wt * val[z], __builtin_amdgcn_fractf(lu),
-                                       __builtin_amdgcn_fractf(lv));
-                        } else {
-                            splat_global(qk, g, su, sv, wt * val[z]);
-                        }
+            for (int z = 0; z < BP_NZ; ++z) {
+                if (z < zcount) {
+                    const float zc = zc0 + (float)z;
+                    const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
+                    const float sw = g.sid * rW, wt = sw * sw;
+                    const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
+                    const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
+                    if (staged) {
+                        const float lu = su - (float)fp.u_lo, lv = sv - (float)fp.v_lo;
+                        const int iu = (int)lu, iv = (int)lv;
+                        splat_tile(tile + iv * BPT_TS + iu, wt * val[z], __builtin_amdgcn_fractf(lu),
+                                   __builtin_amdgcn_fractf(lv), BPT_TS);
+                    } else {
+                        splat_global(qk, g, su, sv, wt * val[z]);
                     }
                 }
             }
         }
         if (staged) {
             __syncthreads();
-            for (int r = ty; r < th; r += 16) {
-                const int gi = v_lo + r;
-                if ((unsigned)gi >= (unsigned)g.nv)
-                    continue;
-                for (int c = tx; c < tw; c += 16) {
-                    const int gj = u_lo + c;
-                    const float t = tile[r * BP_TW + c];
-                    if (t != 0.0f && (unsigned)gj < (unsigned)g.nu)
-                        unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
-                }
-            }
+            flush_tile(tile, fp, g, qk, tid);
         }
     }
 }
@@ -376,17 +517,15 @@ hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *vi
     const dim3 grid((unsigned)(nbx * nby * nzb * batch));
     if (NZ == 32) {
         if (axial)
-            hipLaunchKernelGGL((bpT_cone_kernel<32, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                               nzb);
+            hipLaunchKernelGGL((bpT_axial_kernel<32>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby, nzb);
         else
-            hipLaunchKernelGGL((bpT_cone_kernel<32, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+            hipLaunchKernelGGL((bpT_general_kernel<32>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
                                nzb);
     } else {
         if (axial)
-            hipLaunchKernelGGL((bpT_cone_kernel<16, true>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                               nzb);
+            hipLaunchKernelGGL((bpT_axial_kernel<16>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby, nzb);
         else
-            hipLaunchKernelGGL((bpT_cone_kernel<16, false>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
+            hipLaunchKernelGGL((bpT_general_kernel<16>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
                                nzb);
     }
     return hipGetLastError();
