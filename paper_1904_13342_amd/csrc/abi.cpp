@@ -280,7 +280,7 @@ int bp_segment(const ph_geom3d *g)
     const double slope = zmax * g->sdd / g->det_spacing[0] * brick / (wmin * wmin);
     for (int nz = 32; nz >= 32; nz /= 2) {
         const double th = nz * sz * mag / g->det_spacing[0] + slope + 4.0;
-        if (tw <= 64.0 && th <= 128.0)
+        if (tw <= 64.0 && th <= 120.0)
             return nz;
     }
     return 16;

@@ -23,7 +23,8 @@ namespace ph {
 namespace {
 
 constexpr int BP_TW = 64;    // max staged footprint width (detector columns)
-constexpr int BP_TH = 128;   // max staged footprint height (detector rows)
+constexpr int BP_TH = 120;   // max staged footprint height (detector rows)
+constexpr int BP_TS = 65;    // tile row stride: rows start in different LDS banks
 
 template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
@@ -34,7 +35,7 @@ __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int
 // bilinear fetch at tile-local coordinates, unit-stride columns
 __device__ __forceinline__ float bilerp_tile(const float *p, float fu, float fv)
 {
-    const float p00 = p[0], p01 = p[1], p10 = p[BP_TW], p11 = p[BP_TW + 1];
+    const float p00 = p[0], p01 = p[1], p10 = p[BP_TS], p11 = p[BP_TS + 1];
     const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
     return fmaf(fv, a1 - a0, a0);
 }
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                                                       const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
                                                       int nby, int nzb)
 {
-    __shared__ float tile[BP_TH * BP_TW];
+    __shared__ float tile[BP_TH * BP_TS];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
     const unsigned lin = blockIdx.x;
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                 const TI *rowp = qk + (size_t)(row_ok ? gi : 0) * g.nu;
                 for (int c = tx; c < tw; c += 16) {
                     const int gj = u_lo + c;
-                    tile[r * BP_TW + c] = (row_ok && (unsigned)gj < (unsigned)g.nu) ? load_f32(rowp + gj) : 0.0f;
+                    tile[r * BP_TS + c] = (row_ok && (unsigned)gj < (unsigned)g.nu) ? load_f32(rowp + gj) : 0.0f;
                 }
             }
             __syncthreads();
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                     for (int z = 0; z < BP_NZ; ++z) {
                         const float sv = fmaf((float)z, dvz, sv0);
                         const int iv = (int)sv;
-                        acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TW, fu, __builtin_amdgcn_fractf(sv)), acc[z]);
+                        acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TS, fu, __builtin_amdgcn_fractf(sv)), acc[z]);
                     }
                 } else {
 #pragma unroll
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                         if (z < zcount) {
                             const float sv = fmaf((float)z, dvz, sv0);
                             const int iv = (int)sv;
-                            acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TW, fu, __builtin_amdgcn_fractf(sv)),
+                            acc[z] = fmaf(wt, bilerp_tile(col + iv * BP_TS, fu, __builtin_amdgcn_fractf(sv)),
                                           acc[z]);
                         }
                     }
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                     if (staged) {
                         const float lu = su - (float)u_lo, lv = sv - (float)v_lo;
                         const int iu = (int)lu, iv = (int)lv;
-                        acc[z] = fmaf(wt, bilerp_tile(tile + iv * BP_TW + iu, __builtin_amdgcn_fractf(lu),
+                        acc[z] = fmaf(wt, bilerp_tile(tile + iv * BP_TS + iu, __builtin_amdgcn_fractf(lu),
                                                       __builtin_amdgcn_fractf(lv)),
                                       acc[z]);
                     } else {

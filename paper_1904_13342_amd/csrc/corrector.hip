@@ -59,14 +59,14 @@ __device__ __forceinline__ float pixel_weight(const FilterArgs &a, int k, int i,
     return a.W_red[(size_t)k * a.nu + j] * a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
 }
 
-// MAXF = frequencies (and detector pixels) per thread: M <= 256 * MAXF
-template <int MAXF>
+template <int M>
 __global__ void __launch_bounds__(256) corrector_grad_kernel(FilterArgs a, int splits, const float *__restrict__ p,
                                                              const float *__restrict__ gq, float *__restrict__ dK,
                                                              float *__restrict__ dW)
 {
+    constexpr int MAXF = (M + 255) / 256;   // frequencies (and detector pixels) per thread
     extern __shared__ float2 lds[];
-    const int M = a.M, half = M >> 1;
+    constexpr int half = M >> 1;
     float2 *buf = lds, *tw = lds + M;
     const int tid = threadIdx.x;
     const int i = blockIdx.x % a.nv, split = blockIdx.x / a.nv;
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) corrector_grad_kernel(FilterArgs a, int s
             buf[n] = z;
         }
         __syncthreads();
-        transform<-1>(buf, tw, M, a.log2M);
+        transform_c<-1, M>(buf, tw);
 #pragma unroll
         for (int t = 0; t < MAXF; ++t) {
             const int f = tid + 256 * t;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) corrector_grad_kernel(FilterArgs a, int s
             buf[n] = z;
         }
         __syncthreads();
-        transform<-1>(buf, tw, M, a.log2M);
+        transform_c<-1, M>(buf, tw);
 #pragma unroll
         for (int t = 0; t < MAXF; ++t) {
             const int f = tid + 256 * t;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(256) corrector_grad_kernel(FilterArgs a, int s
             }
         }
         __syncthreads();
-        transform<1>(buf, tw, M, a.log2M);   // M * (dL/dr_a + i dL/dr_b)
+        transform_c<1, M>(buf, tw);   // M * (dL/dr_a + i dL/dr_b)
         const float inv = 1.0f / (float)M;
 #pragma unroll
         for (int t = 0; t < MAXF; ++t) {
@@ -210,10 +210,18 @@ hipError_t launch_corrector_grad(const FilterArgs &a, const float *p, const floa
         splits = pairs;
     const size_t lds = ((size_t)a.M + a.M / 2) * sizeof(float2);
     const dim3 grid((unsigned)(a.nv * splits));
-    if (a.M <= 1024)
-        hipLaunchKernelGGL(corrector_grad_kernel<4>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW);
-    else
-        hipLaunchKernelGGL(corrector_grad_kernel<16>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW);
+    switch (a.log2M) {
+    case 4: hipLaunchKernelGGL(corrector_grad_kernel<16>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 5: hipLaunchKernelGGL(corrector_grad_kernel<32>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 6: hipLaunchKernelGGL(corrector_grad_kernel<64>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 7: hipLaunchKernelGGL(corrector_grad_kernel<128>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 8: hipLaunchKernelGGL(corrector_grad_kernel<256>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 9: hipLaunchKernelGGL(corrector_grad_kernel<512>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 10: hipLaunchKernelGGL(corrector_grad_kernel<1024>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 11: hipLaunchKernelGGL(corrector_grad_kernel<2048>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    case 12: hipLaunchKernelGGL(corrector_grad_kernel<4096>, grid, dim3(256), lds, s, a, splits, p, gq, dK, dW); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

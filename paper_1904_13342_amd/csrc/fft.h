@@ -144,5 +144,65 @@ __device__ __forceinline__ void transform(float2 *buf, const float2 *tw, int M, 
         stockham_pass<2, DIR>(buf, tw, M, Ns);
 }
 
+// The same passes with the transform length fixed at compile time: index
+// arithmetic folds to constants and the per-thread item loop unrolls exactly.
+template <int R, int DIR, int M, int NS>
+__device__ __forceinline__ void stockham_pass_c(float2 *buf, const float2 *tw)
+{
+    constexpr int items = M / R;
+    constexpr int ITER = (items + WF_THREADS - 1) / WF_THREADS;
+    constexpr int twscale = M / (NS * R);
+    constexpr int half = M / 2;
+    float2 v[ITER][R];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int j = threadIdx.x + it * WF_THREADS;
+        if (items % WF_THREADS == 0 || j < items) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = buf[j + r * items];
+                if (NS > 1 && r > 0) {
+                    const int t = (jm * r * twscale) & (M - 1);
+                    float2 w = tw[t & (half - 1)];
+                    if (t >= half)
+                        w = make_float2(-w.x, -w.y);
+                    if (DIR > 0)
+                        w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[it][r] = x;
+            }
+            dft<R, DIR>(v[it]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int j = threadIdx.x + it * WF_THREADS;
+        if (items % WF_THREADS == 0 || j < items) {
+            const int jm = j & (NS - 1);
+            const int base = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                buf[base + r * NS] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int M, int NS = 1>
+__device__ __forceinline__ void transform_c(float2 *buf, const float2 *tw)
+{
+    if constexpr (NS * 8 <= M) {
+        stockham_pass_c<8, DIR, M, NS>(buf, tw);
+        transform_c<DIR, M, NS * 8>(buf, tw);
+    } else if constexpr (NS * 4 == M) {
+        stockham_pass_c<4, DIR, M, NS>(buf, tw);
+    } else if constexpr (NS * 2 == M) {
+        stockham_pass_c<2, DIR, M, NS>(buf, tw);
+    }
+}
+
 }  // namespace lds_fft
 }  // namespace ph

@@ -34,12 +34,12 @@ __device__ __forceinline__ float weighted(const FilterArgs &a, const T *in, long
     return w * load_f32(in + (size_t)row * a.nu + j);
 }
 
-template <typename T>
+template <typename T, int M>
 __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a, const T *__restrict__ in,
                                                                    float *__restrict__ out, long rows)
 {
     extern __shared__ float2 lds[];
-    const int M = a.M, half = M >> 1;
+    constexpr int half = M >> 1;
     float2 *buf = lds, *tw = lds + M;
     const int tid = threadIdx.x;
     const long pairs = (rows + 1) / 2;
@@ -59,15 +59,19 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
             buf[n] = z;
         }
         __syncthreads();
-        transform<-1>(buf, tw, M, a.log2M);
+        transform_c<-1, M>(buf, tw);
         // multiply by the symmetrised real response
-        for (int n = tid; n < M; n += WF_THREADS) {
-            const float kf = 0.5f * (a.K[n] + a.K[(M - n) & (M - 1)]);
-            buf[n].x *= kf;
-            buf[n].y *= kf;
+#pragma unroll
+        for (int t = 0; t < (M + WF_THREADS - 1) / WF_THREADS; ++t) {
+            const int n = tid + t * WF_THREADS;
+            if (n < M) {
+                const float kf = 0.5f * (a.K[n] + a.K[(M - n) & (M - 1)]);
+                buf[n].x *= kf;
+                buf[n].y *= kf;
+            }
         }
         __syncthreads();
-        transform<1>(buf, tw, M, a.log2M);
+        transform_c<1, M>(buf, tw);
         for (int n = tid; n < a.nu; n += WF_THREADS) {
             const float2 z = buf[n];
             out[(size_t)ra * a.nu + n] = z.x * inv;
@@ -78,16 +82,34 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
     }
 }
 
-template <typename T>
-hipError_t wf(const FilterArgs &a, const void *in, float *out, hipStream_t s)
+template <typename T, int M>
+hipError_t wf_m(const FilterArgs &a, const void *in, float *out, hipStream_t s)
 {
     const long rows = (long)a.batch * a.n_proj * a.nv;
     const long pairs = (rows + 1) / 2;
-    const size_t lds = ((size_t)a.M + a.M / 2) * sizeof(float2);
+    const size_t lds = ((size_t)M + M / 2) * sizeof(float2);
     const long max_groups = 256L * 8;   // enough resident workgroups for 256 CUs
     const unsigned grid = (unsigned)(pairs < max_groups ? pairs : max_groups);
-    hipLaunchKernelGGL((weight_filter_kernel<T>), dim3(grid), dim3(WF_THREADS), lds, s, a, (const T *)in, out, rows);
+    hipLaunchKernelGGL((weight_filter_kernel<T, M>), dim3(grid), dim3(WF_THREADS), lds, s, a, (const T *)in, out,
+                       rows);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t wf(const FilterArgs &a, const void *in, float *out, hipStream_t s)
+{
+    switch (a.log2M) {
+    case 4: return wf_m<T, 16>(a, in, out, s);
+    case 5: return wf_m<T, 32>(a, in, out, s);
+    case 6: return wf_m<T, 64>(a, in, out, s);
+    case 7: return wf_m<T, 128>(a, in, out, s);
+    case 8: return wf_m<T, 256>(a, in, out, s);
+    case 9: return wf_m<T, 512>(a, in, out, s);
+    case 10: return wf_m<T, 1024>(a, in, out, s);
+    case 11: return wf_m<T, 2048>(a, in, out, s);
+    case 12: return wf_m<T, 4096>(a, in, out, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
