@@ -25,6 +25,8 @@ constexpr int FP_D = 8;                // slab depth (planes along A)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
 constexpr int FP_LDS_FLOATS = 9984;    // 39 KiB slab capacity: four workgroups per CU
 constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
+constexpr int FP_VG = 8;               // views of one tile scheduled together
+constexpr int FP_XCDS = 8;             // accelerator complex dies, each with its own L2
 
 template <typename T>
 __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix, int iy, int iz)
@@ -228,16 +230,33 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
     return acc;
 }
 
+// Work order.  Consecutive views of one detector tile sample nearly the same
+// cells, so they run side by side and share the slabs in L2: work item
+// w = ((b * n_groups + group) * n_tiles + tile) * FP_VG + view-in-group.
+// Workgroups are dealt to the 8 XCDs round-robin (XCD = blockIdx mod 8),
+// each with its own L2, so every XCD is given one contiguous range of work
+// items.
+struct FpWork {
+    int ntu, ntiles, ngroups, total;   // total = batch * ngroups * ntiles * FP_VG
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView *__restrict__ views,
-                                                      const T *__restrict__ vol, T *__restrict__ proj)
+                                                      const T *__restrict__ vol, T *__restrict__ proj, FpWork wk)
 {
     __shared__ float slab[FP_LDS_FLOATS];
     __shared__ int s_range[2];
     const int tid = threadIdx.x;
-    const int j0 = blockIdx.x * FP_TILE, i0 = blockIdx.y * FP_TILE;
+    const unsigned per_xcd = gridDim.x / FP_XCDS;
+    const int w = (int)((blockIdx.x % FP_XCDS) * per_xcd + blockIdx.x / FP_XCDS);
+    if (w >= wk.total)
+        return;
+    const int kk = w % FP_VG, t = (w / FP_VG) % wk.ntiles, bg = w / (FP_VG * wk.ntiles);
+    const int k = (bg % wk.ngroups) * FP_VG + kk, b = bg / wk.ngroups;
+    if (k >= g.n_proj)
+        return;
+    const int j0 = (t % wk.ntu) * FP_TILE, i0 = (t / wk.ntu) * FP_TILE;
     const int j = j0 + (tid % FP_TILE), i = i0 + (tid / FP_TILE);
-    const int k = blockIdx.z % g.n_proj, b = blockIdx.z / g.n_proj;
     const bool valid = j < g.nu && i < g.nv;
     const ConeFPView &v = views[k];
     const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;
@@ -286,8 +305,16 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
 template <typename T>
 hipError_t fp_cone(const Geom3D &g, const ConeFPView *views, const void *vol, void *proj, int batch, hipStream_t s)
 {
-    dim3 grid((g.nu + FP_TILE - 1) / FP_TILE, (g.nv + FP_TILE - 1) / FP_TILE, g.n_proj * batch);
-    hipLaunchKernelGGL((fp_cone_kernel<T>), grid, dim3(256), 0, s, g, views, (const T *)vol, (T *)proj);
+    FpWork wk;
+    wk.ntu = (g.nu + FP_TILE - 1) / FP_TILE;
+    wk.ntiles = wk.ntu * ((g.nv + FP_TILE - 1) / FP_TILE);
+    wk.ngroups = (g.n_proj + FP_VG - 1) / FP_VG;
+    const long total = (long)batch * wk.ngroups * wk.ntiles * FP_VG;
+    if (total > (1L << 30))
+        return hipErrorInvalidConfiguration;
+    wk.total = (int)total;
+    const unsigned grid = (unsigned)((total + FP_XCDS - 1) / FP_XCDS * FP_XCDS);
+    hipLaunchKernelGGL((fp_cone_kernel<T>), dim3(grid), dim3(256), 0, s, g, views, (const T *)vol, (T *)proj, wk);
     return hipGetLastError();
 }
 
