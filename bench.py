@@ -37,6 +37,35 @@ PEAK_HBM_GBS = 8000.0
 OPS_PER_UPDATE = 11.0      # back-projection: v coordinate, floor/fract, 3 lerps, accumulate
 OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7 lerps, accumulate
 
+# HBM bytes per launch at 512^3 from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
+# what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524308 KiB, WRITE_SIZE 1048580 KiB).
+# A record holds for the kernel sources it was taken on (hash below); after any change the traffic is reported as null.
+COPY_BYTES = 1 << 30
+COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.0, 1048580.0
+MEASURED_TRAFFIC = {
+    "fp_cone": {"fetch_kib": 7.61368e7, "write_kib": 1.21983e6,
+                "sources": ("cone_fp.hip", "device_util.h", "common.h"), "sha256_16": "e2d3b21ec899ed78"},
+    "bp_cone": {"fetch_kib": 9.3219e6, "write_kib": 524288.0,
+                "sources": ("cone_bp.hip", "device_util.h", "common.h"), "sha256_16": "3c0bf9c76253fff8"},
+    "weight_filter": {"fetch_kib": 563968.0, "write_kib": 1.10592e6,
+                      "sources": ("filter.hip", "fft.h", "common.h"), "sha256_16": "dafff71523ff20b7"},
+}
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of kernel `name`, or None if its sources changed since the counters were taken."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(name)
+    if rec is None:
+        return None
+    m = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_1904_13342_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    if m.hexdigest()[:16] != rec["sha256_16"]:
+        return None
+    return rec["fetch_kib"] * COPY_BYTES / COPY_FETCH_KIB + rec["write_kib"] * COPY_BYTES / COPY_WRITE_KIB
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -46,8 +75,9 @@ def parse():
     ap.add_argument("--config", default="cone3d_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("fdk", "corrector"), default="fdk",
-                    help="fdk: the projector / FDK hot path (default); corrector: the learned-corrector training run")
+    ap.add_argument("--workload", choices=("fdk", "corrector", "copyref"), default="fdk",
+                    help="fdk: the projector / FDK hot path (default); corrector: the learned-corrector training run; "
+                         "copyref: one plain 1 GiB device copy, the reference that scales the HBM byte counters")
     ap.add_argument("--train-steps", type=int, default=2000, help="corrector: Adam steps")
     ap.add_argument("--batch", type=int, default=16, help="corrector: training phantoms per step")
     ap.add_argument("--sigma", type=float, default=0.01, help="corrector: Gaussian noise on the line integrals")
@@ -238,6 +268,15 @@ def main():
     if args.workload == "corrector":
         corrector_main(args)
         return
+    if args.workload == "copyref":
+        import torch
+        x = torch.ones(COPY_BYTES // 4, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copyref", "bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES}), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -305,12 +344,13 @@ def main():
                     "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "units_per_launch": updates,
                     "unit_name": "voxel-view updates", "ops_per_unit": OPS_PER_UPDATE},
     }
-    for kv in kernels.values():
+    for name, kv in kernels.items():
         kv["frac"] = kv["achieved"] / kv["peak"]
+        kv["traffic"] = measured_traffic(name)
     dom_name = max(kernels, key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
-                "unit": dom["unit"], "frac": dom["frac"], "traffic": None}
+                "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"]}
 
     cpu = None
     if not args.no_cpu_baseline:
