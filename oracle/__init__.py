@@ -357,9 +357,62 @@ def adam(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return np.asarray(param, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
+# ------------------------------------------------- TV-regularised iteration
+#
+# Sec. III.B.1 / Eq. 7: an additive layer holding the image, forward
+# projected, trained on the l2 data term plus lambda * TV.  TV is the
+# isotropic total variation with forward differences, no difference across
+# the last row / column / plane, and a smoothing constant eps.
+
+def tv(x, eps):
+    """TV_eps(x) = sum_q sqrt(sum_d (x[q + e_d] - x[q])^2 + eps^2) over a 2D
+    [ny, nx] or 3D [nz, ny, nx] array; differences that would leave the grid
+    are zero."""
+    x = np.asarray(x, dtype=np.float64)
+    s = np.full(x.shape, eps * eps)
+    for ax in range(x.ndim):
+        d = np.zeros_like(x)
+        sl_hi = [slice(None)] * x.ndim
+        sl_lo = [slice(None)] * x.ndim
+        sl_hi[ax] = slice(1, None)
+        sl_lo[ax] = slice(0, -1)
+        d[tuple(sl_lo)] = x[tuple(sl_hi)] - x[tuple(sl_lo)]
+        s += d * d
+    return float(np.sqrt(s).sum())
+
+
+def tv_grad(x, eps):
+    """Gradient of ``tv``: for phi(q) the summand at q and D_d(q) its
+    differences, dTV/dx[p] = -sum_d D_d(p) / phi(p)
+    + sum_d [p - e_d in the grid] D_d(p - e_d) / phi(p - e_d)."""
+    x = np.asarray(x, dtype=np.float64)
+    D = []
+    s = np.full(x.shape, eps * eps)
+    for ax in range(x.ndim):
+        d = np.zeros_like(x)
+        sl_hi = [slice(None)] * x.ndim
+        sl_lo = [slice(None)] * x.ndim
+        sl_hi[ax] = slice(1, None)
+        sl_lo[ax] = slice(0, -1)
+        d[tuple(sl_lo)] = x[tuple(sl_hi)] - x[tuple(sl_lo)]
+        D.append(d)
+        s += d * d
+    phi = np.sqrt(s)
+    g = np.zeros_like(x)
+    for ax, d in enumerate(D):
+        q = d / phi
+        g -= q
+        sl_hi = [slice(None)] * x.ndim
+        sl_lo = [slice(None)] * x.ndim
+        sl_hi[ax] = slice(1, None)
+        sl_lo[ax] = slice(0, -1)
+        g[tuple(sl_hi)] += q[tuple(sl_lo)]
+    return g
+
+
 __all__ = [
     "build", "geom", "num_threads", "project", "project_adjoint", "count_samples", "backproject",
     "backproject_adjoint", "tau", "fft_size", "ramlak_filter", "circular_filter", "ramlak_response",
     "ramp_response", "cosine_weights", "redundancy_weights", "parker", "projection_matrices", "weight",
-    "filter_projections", "fbp", "mse", "corrector_grad", "corrector_forward", "adam",
+    "filter_projections", "fbp", "mse", "corrector_grad", "corrector_forward", "adam", "tv", "tv_grad",
 ]
