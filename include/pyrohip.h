@@ -264,6 +264,24 @@ int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *gra
 int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, float lr, float beta1,
                  float beta2, float eps, int t, void *stream);
 
+/* ---------------------------------------- TV-regularised iterative recon
+ * Sec. III.B.1, Eq. 7: the image is the weight of an additive layer,
+ * forward-projected and trained on the l2 data term plus lambda * TV(x).  One
+ * iteration is ph_project_* (A x), ph_mse_grad (residual gradient),
+ * ph_project_adjoint_* (A^T), ph_tv_3d (regulariser) and ph_adam_step.
+ *
+ * Isotropic total variation with forward differences (none across the last
+ * row / column / plane) and smoothing eps:
+ *   TV(x) = sum_q sqrt(sum_d (x[q + e_d] - x[q])^2 + eps^2).
+ *   vol   : device float[batch][nz][ny][nx] (nz = 1 for an image [ny][nx]);
+ *   grad  : device float, same shape, or NULL: grad += weight * dTV/dx;
+ *   value : device double[batch] or NULL: TV of each item (FP32 terms summed
+ *           in FP64 with atomics, so the last bits may vary).
+ * eps > 0 and weight finite (else PH_ERR_VALUE); sizes and batch >= 1 (else
+ * PH_ERR_SHAPE).  grad must not alias vol. */
+int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, float weight, float *grad,
+             double *value, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,5 +12,6 @@ from .ops import *  # noqa: E402,F401,F403
 from .ops import __all__ as _ops_all  # noqa: E402
 from . import autograd  # noqa: E402,F401
 from .corrector import LearnedCorrector  # noqa: E402,F401
+from .iterative import TVReconstruction  # noqa: E402,F401
 
-__all__ = list(_ops_all) + ["autograd", "LearnedCorrector"]
+__all__ = list(_ops_all) + ["autograd", "LearnedCorrector", "TVReconstruction"]

@@ -78,6 +78,7 @@ SIGNATURES = {
     "ph_fbp_fan2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fdk_cone3d": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _P, _SZ, _I, _I, _P]),
     "ph_filter_response": (_I, [_I, _I, ctypes.c_double, _FP]),
+    "ph_tv_3d": (_I, [_P, _I, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "ph_mse_grad": (_I, [_P, _P, _P, _SZ, _P, _P, _P]),
     "ph_corrector_grad_3d": (_I, [_G3, _P, _P, _P, _I, _P, _P, _P, _P, _I, _P]),
     "ph_adam_step": (_I, [_P, _P, _P, _P, _SZ, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I,

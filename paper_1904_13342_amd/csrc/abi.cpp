@@ -1037,4 +1037,18 @@ int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, 
     return to_status(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
 }
 
+int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, float weight, float *grad, double *value,
+             void *stream)
+{
+    if (!vol)
+        return PH_ERR_NULL;
+    if (nz < 1 || ny < 1 || nx < 1 || batch < 1 || (double)nx * ny * nz * batch > 1e12)
+        return PH_ERR_SHAPE;
+    if (!(std::isfinite(eps) && eps > 0.0f) || !std::isfinite(weight))
+        return PH_ERR_VALUE;
+    if (!grad && !value)
+        return PH_OK;
+    return to_status(launch_tv(vol, nx, ny, nz, batch, eps, weight, grad, value, (hipStream_t)stream));
+}
+
 }  // extern "C"

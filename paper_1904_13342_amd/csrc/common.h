@@ -128,4 +128,8 @@ hipError_t launch_corrector_grad(const FilterArgs &a, const float *proj, const f
 hipError_t launch_adam(float *param, const float *grad, float *m, float *v, size_t n, float lr, float b1, float b2,
                        float eps, int t, hipStream_t stream);
 
+// Total variation (value and / or accumulated gradient)
+hipError_t launch_tv(const float *vol, int nx, int ny, int nz, int batch, float eps, float weight, float *grad,
+                     double *value, hipStream_t stream);
+
 }  // namespace ph

@@ -1,0 +1,69 @@
+"""TV-regularised iterative reconstruction as a network (Sec. III.B.1, Eq. 7).
+
+The image is the weight of an additive layer fed with zeros, so the network
+output is the image itself; it is forward projected and trained on
+
+    L(x) = mean((A x - p)^2) + lam * TV_eps(x)
+
+with Adam, starting from zero.  (Eq. 7 writes the data term as a squared
+norm; the mean only rescales lam.)  One iteration is five library calls on
+the caller's stream: the forward projection, the residual gradient, the
+matched adjoint A^T, the TV gradient added in place and the Adam step.  This
+module only owns the buffers.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+
+_PROJECT = {"par2d": (ops.project_par2d, ops.project_adjoint_par2d, 2),
+            "fan2d": (ops.project_fan2d, ops.project_adjoint_fan2d, 2),
+            "cone3d": (ops.project_cone3d, ops.project_adjoint_cone3d, 3)}
+
+
+class TVReconstruction:
+    """Iterative reconstruction of the measured projections p.
+
+    kind : "par2d", "fan2d" or "cone3d" (g and traj as for the operators);
+    p    : FP32 device projections, [n_proj, nu] / [n_proj, nv, nu] or with a
+           leading batch axis;
+    lam, eps : TV weight and smoothing; lr, betas, adam_eps : Adam.
+    """
+
+    def __init__(self, kind, g, traj, p, lam=1e-3, eps=1e-3, lr=1e-2, betas=(0.9, 0.999), adam_eps=1e-8):
+        if kind not in _PROJECT:
+            raise ValueError(f"kind must be one of {sorted(_PROJECT)}")
+        self.project, self.adjoint, self.dims = _PROJECT[kind]
+        self.g, self.traj, self.p = g, traj, p
+        self.lam, self.eps, self.lr, self.betas, self.adam_eps = lam, eps, lr, betas, adam_eps
+        lead = tuple(p.shape[:-self.dims])   # batch axes (the projection tail has `dims` axes)
+        shape = lead + tuple(g.vol_shape)
+        self.x = torch.zeros(shape, dtype=torch.float32, device=p.device)
+        self.m = torch.zeros_like(self.x)
+        self.v = torch.zeros_like(self.x)
+        self.t = 0
+        self._r = torch.empty_like(p)
+        self._gr = torch.empty_like(p)
+        self._gx = torch.empty_like(self.x)
+
+    def step(self):
+        """One Adam step; returns (data term, TV) at the iterate before it,
+        as device scalars."""
+        self.project(self.g, self.traj, self.x, out=self._r)
+        data, _ = ops.mse_grad(self._r, self.p, grad=self._gr)
+        self.adjoint(self.g, self.traj, self._gr, out=self._gx)
+        tv, _ = ops.tv(self.x, self.eps, self.dims, weight=self.lam, grad=self._gx)
+        self.t += 1
+        b1, b2 = self.betas
+        ops.adam_step(self.x, self._gx, self.m, self.v, self.t, lr=self.lr, beta1=b1, beta2=b2, eps=self.adam_eps)
+        return data, tv
+
+    def run(self, iters):
+        out = None
+        for _ in range(iters):
+            out = self.step()
+        return out
+
+
+__all__ = ["TVReconstruction"]

@@ -316,6 +316,38 @@ def adam_step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return param
 
 
+def tv(x, eps, dims, weight=1.0, grad=None, want_value=True):
+    """Isotropic total variation of x, whose last `dims` (2 or 3) axes are
+    spatial ([..., ny, nx] or [..., nz, ny, nx]) and the others a batch, FP32.
+    Returns (value, grad): value is a float64 device tensor with the batch
+    shape (a scalar when there is no batch axis); grad, when given, is
+    updated in place: grad += weight * dTV/dx."""
+    if dims not in (2, 3):
+        raise ValueError("dims must be 2 or 3")
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float32:
+        raise ValueError("x must be a float32 GPU tensor")
+    if not x.is_contiguous() or x.dim() < dims:
+        raise ValueError(f"x must be contiguous with at least {dims} dimensions")
+    nx, ny = x.shape[-1], x.shape[-2]
+    nz = x.shape[-3] if dims == 3 else 1
+    lead = tuple(x.shape[:-dims])
+    batch = 1
+    for n in lead:
+        batch *= n
+    if grad is not None:
+        _f32_like(grad, "grad", x.numel())
+        if grad.data_ptr() == x.data_ptr():
+            raise ValueError("grad must not alias x")
+    value = torch.empty(max(batch, 1), dtype=torch.float64, device=x.device) if want_value else None
+    status = lib().ph_tv_3d(ctypes.c_void_p(x.data_ptr()), nz, ny, nx, batch, float(eps), float(weight),
+                            None if grad is None else ctypes.c_void_p(grad.data_ptr()),
+                            None if value is None else ctypes.c_void_p(value.data_ptr()), _stream(x))
+    check("ph_tv_3d", status)
+    if value is not None:
+        value = value.reshape(lead) if lead else value[0]
+    return value, grad
+
+
 def workspace_bytes_2d(g, batch=1):
     return int(lib().ph_workspace_bytes_2d(ctypes.byref(g), int(batch)))
 
@@ -380,5 +412,5 @@ __all__ = [
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "filter_response", "mse_grad", "corrector_grad_3d", "adam_step", "version",
+    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "mse_grad", "corrector_grad_3d", "adam_step", "version",
 ]

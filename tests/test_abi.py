@@ -207,6 +207,15 @@ def test_rejects_bad_corrector_arguments(ph, L):
         assert st == -8, key
 
 
+def test_rejects_bad_tv_arguments(L):
+    assert L.ph_tv_3d(None, 1, 4, 4, 1, 0.1, 1.0, FAKE, None, None) == -1
+    assert L.ph_tv_3d(FAKE, 0, 4, 4, 1, 0.1, 1.0, FAKE, None, None) == -2
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 0, 0.1, 1.0, FAKE, None, None) == -2
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.0, 1.0, FAKE, None, None) == -8
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.1, float("nan"), FAKE, None, None) == -8
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.1, 1.0, None, None, None) == 0   # nothing requested: no launch
+
+
 def test_filter_response_matches_oracle(L, ora):
     for kind, ref_fn in ((0, ora.ramlak_response), (1, ora.ramp_response)):
         for M in (16, 1024):

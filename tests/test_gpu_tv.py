@@ -1,0 +1,129 @@
+"""TV-regularised iterative reconstruction on the GPU (Sec. III.B.1, Eq. 7):
+parity of the total-variation kernel with the oracle (value and gradient,
+2D, 3D, batched, accumulate), one iteration's gradient and Adam update
+against the oracle's chain, and a sparse-view run (30 parallel views over
+180 degrees, 2% noise) that must end below FBP's error."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gpu_common as gc
+import synth
+from gpu_common import FP32_TOL, as_f32, rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ph():
+    gc.device()
+    import paper_1904_13342_amd as ph
+    return ph
+
+
+@pytest.mark.parametrize("shape,dims", [((45, 31), 2), ((3, 45, 31), 2), ((23, 29, 35), 3), ((2, 9, 17, 40), 3),
+                                        ((1, 1), 2), ((7, 1, 5), 3)])
+def test_tv_parity(ph, ora, shape, dims):
+    say(f"[tv] shape {shape} dims {dims}")
+    x = as_f32(synth.random_array(shape, 11))
+    g0 = as_f32(synth.random_array(shape, 12))
+    eps, w = 0.05, 0.7
+    X, G = to_dev(x), to_dev(g0)
+    val, _ = ph.tv(X, eps, dims, weight=w, grad=G)
+    lead = shape[:len(shape) - dims]
+    xs = x.reshape((-1,) + shape[len(shape) - dims:])
+    ref_v = np.array([ora.tv(xi, eps) for xi in xs]).reshape(lead)
+    ref_g = g0 + w * np.stack([ora.tv_grad(xi, eps) for xi in xs]).reshape(shape)
+    ev = np.abs(to_np(val) - ref_v).max() / np.abs(ref_v).max()
+    eg = rel_l2(to_np(G), ref_g)
+    say(f"  value rel {ev:.2e}  grad rel-L2 {eg:.2e}")
+    assert ev < 1e-6 and eg < FP32_TOL
+
+
+def test_tv_full_size_256(ph, ora):
+    spec = synth.config("cone3d_256_short")
+    say("[tv] 256^3 phantom")
+    x = gc.phantom(spec)
+    X = to_dev(x)
+    G = torch.zeros_like(X)
+    val, _ = ph.tv(X, 1e-3, 3, grad=G)
+    rv = ora.tv(x, 1e-3)
+    ev = abs(float(val) - rv) / rv
+    eg = rel_l2(to_np(G), ora.tv_grad(x, 1e-3))
+    say(f"  value rel {ev:.2e}  grad rel-L2 {eg:.2e}")
+    assert ev < 1e-6 and eg < FP32_TOL
+
+
+def test_tv_rejects_bad_arguments(ph):
+    from paper_1904_13342_amd._lib import PyroHipError
+    x = torch.zeros((4, 4), device=gc.device())
+    with pytest.raises(PyroHipError):
+        ph.tv(x, 0.0, 2)
+    with pytest.raises(ValueError):
+        ph.tv(x, 0.1, 2, grad=x)
+
+
+SPARSE = synth.config("par2d_64").with_(vol_shape=(96, 96), det_shape=(137,), n_proj=30)
+
+
+def _sparse_problem(ora, spec, seed=0, noise=0.02):
+    f = gc.phantom(spec, seed=seed)
+    p = ora.project(spec, f)
+    rng = np.random.default_rng(100 + seed)
+    p_noisy = p + noise * np.abs(p).max() * rng.standard_normal(p.shape)
+    return f, as_f32(p_noisy)
+
+
+def test_iteration_parity(ph, ora):
+    """From a nonzero iterate: the gradient 2 A^T (A x - p) / n_p + lam dTV/dx
+    and the Adam update match the oracle's chain."""
+    spec = SPARSE
+    f, p = _sparse_problem(ora, spec)
+    g = ph.from_spec(spec)
+    rv = ph.ray_vectors_2d(g)
+    lam, eps = 2e-3, 1e-2
+    it = ph.TVReconstruction("par2d", g, rv, to_dev(p), lam=lam, eps=eps, lr=1e-2)
+    x0 = as_f32(0.5 * f + 0.05 * synth.random_array(f.shape, 5))
+    it.x.copy_(to_dev(x0))
+    data, tvv = it.step()
+    r = ora.project(spec, x0)
+    L, gr = ora.mse(r, p)
+    grad = ora.project_adjoint(spec, gr) + lam * ora.tv_grad(x0, eps)
+    x1, _, _ = ora.adam(x0, grad, np.zeros_like(x0), np.zeros_like(x0), 1, lr=1e-2)
+    eg = rel_l2(to_np(it._gx), grad)
+    # Adam's first step is about lr * sign(g): compare where g is clearly
+    # nonzero (elsewhere FP32 and FP64 may round g to opposite signs) and
+    # bound the step everywhere
+    dx = to_np(it.x) - x0
+    keep = np.abs(grad) > 1e-4 * np.abs(grad).max()
+    ex = rel_l2(dx[keep], (x1 - x0)[keep])
+    assert np.abs(dx).max() <= 1e-2 * (1 + 1e-5)
+    say(f"[tv iteration] data {float(data):.6e} vs {L:.6e}; TV {float(tvv):.6e} vs {ora.tv(x0, eps):.6e}; "
+        f"grad rel-L2 {eg:.2e}; update rel-L2 {ex:.2e}")
+    assert abs(float(data) - L) <= 1e-5 * L
+    assert abs(float(tvv) - ora.tv(x0, eps)) <= 1e-5 * ora.tv(x0, eps)
+    assert eg < FP32_TOL
+    assert ex < 1e-5
+
+
+def test_sparse_view_tv_beats_fbp(ph, ora):
+    spec = SPARSE
+    f, p = _sparse_problem(ora, spec, seed=3)
+    g = ph.from_spec(spec)
+    rv = ph.ray_vectors_2d(g)
+    P = to_dev(p)
+    fbp = to_np(ph.fbp_par2d(g, rv, P))
+    it = ph.TVReconstruction("par2d", g, rv, P, lam=3e-3, eps=1e-2, lr=2e-2)
+    first = None
+    for k in range(400):
+        data, tvv = it.step()
+        if k == 0:
+            first = float(data)
+    last = float(data)
+    x = to_np(it.x)
+    rm = lambda a: float(np.sqrt(np.mean((a - f) ** 2)))
+    say(f"[sparse TV] data term {first:.4e} -> {last:.4e}; RMSE TV {rm(x):.4e} vs FBP {rm(fbp):.4e}")
+    assert last < 0.05 * first
+    assert rm(x) < rm(fbp)
