@@ -286,16 +286,15 @@ def tv_main(args):
     rmse = lambda x: float(((x.double() - f.double()) ** 2).mean().sqrt())
     rmse_fbp = rmse(ph.fbp_par2d(g, rv, p))
     it = ph.TVReconstruction("par2d", g, rv, p, lam=args.lam, eps=1e-2, lr=2e-2)
-    for _ in range(10):   # warm-up iterations are part of the run
-        it.step()
+    it.run(10)   # warm-up iterations are part of the run
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.iters - 10):
-        data, tvv = it.step()
+    out = it.run(args.iters - 10)   # one library call: the loop runs inside the library
     e1.record()
     torch.cuda.synchronize()
+    data, tvv = out[0], out[1]
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / (args.iters - 10)
     line = {

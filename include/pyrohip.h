@@ -282,6 +282,35 @@ int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, 
 int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, float weight, float *grad,
              double *value, void *stream);
 
+/* n_iter iterations of the TV-regularised reconstruction in one call (the
+ * five steps above, issued from the library without a host round trip):
+ *   L(x) = mean((A x - p)^2) + lam * TV_eps(x), Adam with steps t0+1 .. t0+n_iter.
+ *   proj     : device float projections [batch][n_proj](nv)[nu] (measured p);
+ *   x, m, v  : device float [batch] image / volume, Adam moments; updated;
+ *   ws       : device workspace of ph_tv_workspace_bytes_*() bytes;
+ *   data_tv  : device double[1 + batch] or NULL: the data term and the TV of
+ *              each item at the iterate before the last update.
+ * The operator is the matched pair (A, A^T) of the geometry.  Validation as
+ * for the operators; t0 >= 0, n_iter >= 1 (else PH_ERR_SHAPE); lam >= 0,
+ * eps > 0, lr > 0, betas in [0, 1), adam_eps > 0, all finite (else
+ * PH_ERR_VALUE). */
+typedef struct {
+    float lam, eps;                      /* TV weight and smoothing */
+    float lr, beta1, beta2, adam_eps;    /* Adam */
+} ph_tv_params;
+
+size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch);
+size_t ph_tv_workspace_bytes_3d(const ph_geom3d *g, int batch);
+int ph_tv_iterate_par2d(const ph_geom2d *g, const float *ray_vecs, const float *proj, float *x, float *m, float *v,
+                        int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv,
+                        int batch, void *stream);
+int ph_tv_iterate_fan2d(const ph_geom2d *g, const float *ray_vecs, const float *proj, float *x, float *m, float *v,
+                        int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv,
+                        int batch, void *stream);
+int ph_tv_iterate_cone3d(const ph_geom3d *g, const float *mats, const float *proj, float *x, float *m, float *v,
+                         int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv,
+                         int batch, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1051,4 +1051,145 @@ int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, flo
     return to_status(launch_tv(vol, nx, ny, nz, batch, eps, weight, grad, value, (hipStream_t)stream));
 }
 
+size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1 || g->vol_shape[0] < 1 || g->vol_shape[1] < 1)
+        return 0;
+    const size_t np = (size_t)batch * g->n_proj * g->det_shape, nx = (size_t)batch * g->vol_shape[0] * g->vol_shape[1];
+    return 2 * round_up(np * sizeof(float)) + round_up(nx * sizeof(float));
+}
+
+size_t ph_tv_workspace_bytes_3d(const ph_geom3d *g, int batch)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1 || g->vol_shape[0] < 1 ||
+        g->vol_shape[1] < 1 || g->vol_shape[2] < 1)
+        return 0;
+    const size_t np = (size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1];
+    const size_t nx = (size_t)batch * g->vol_shape[0] * g->vol_shape[1] * g->vol_shape[2];
+    return 2 * round_up(np * sizeof(float)) + round_up(nx * sizeof(float));
+}
+
+}  // extern "C"
+
+namespace {
+
+bool tv_params_ok(const ph_tv_params *p)
+{
+    auto fin = [](float v) { return std::isfinite(v); };
+    return fin(p->lam) && p->lam >= 0.0f && fin(p->eps) && p->eps > 0.0f && fin(p->lr) && p->lr > 0.0f &&
+           fin(p->beta1) && p->beta1 >= 0.0f && p->beta1 < 1.0f && fin(p->beta2) && p->beta2 >= 0.0f &&
+           p->beta2 < 1.0f && fin(p->adam_eps) && p->adam_eps > 0.0f;
+}
+
+// The iteration loop shared by the three geometries: fwd / adj are the
+// matched operator pair, (nz, ny, nx) the image grid, np / nx_total the
+// element counts of the projections and of the images.
+template <typename Fwd, typename Adj>
+int tv_iterate(Fwd fwd, Adj adj, int nz, int ny, int nxg, size_t np, size_t nimg, const float *proj, float *x,
+               float *m, float *v, int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes,
+               size_t ws_need, double *data_tv, int batch, void *stream)
+{
+    if (!proj || !x || !m || !v || !prm)
+        return PH_ERR_NULL;
+    if (t0 < 0 || n_iter < 1)
+        return PH_ERR_SHAPE;
+    if (!tv_params_ok(prm))
+        return PH_ERR_VALUE;
+    if (!ws || ws_need == 0 || ws_bytes < ws_need)
+        return PH_ERR_WORKSPACE;
+    char *w = (char *)ws;
+    float *r = (float *)w;
+    float *gr = (float *)(w + round_up(np * sizeof(float)));
+    float *gx = (float *)(w + 2 * round_up(np * sizeof(float)));
+    hipStream_t s = (hipStream_t)stream;
+    for (int it = 0; it < n_iter; ++it) {
+        const bool last = it + 1 == n_iter;
+        int st = fwd(x, r);
+        if (st != PH_OK)
+            return st;
+        st = to_status(launch_mse(r, proj, nullptr, np, gr, last ? data_tv : nullptr, s));
+        if (st != PH_OK)
+            return st;
+        st = adj(gr, gx);
+        if (st != PH_OK)
+            return st;
+        st = to_status(launch_tv(x, nxg, ny, nz, batch, prm->eps, prm->lam, gx, last && data_tv ? data_tv + 1 : nullptr,
+                                 s));
+        if (st != PH_OK)
+            return st;
+        st = to_status(launch_adam(x, gx, m, v, nimg, prm->lr, prm->beta1, prm->beta2, prm->adam_eps, t0 + it + 1, s));
+        if (st != PH_OK)
+            return st;
+    }
+    return PH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph_tv_iterate_par2d(const ph_geom2d *g, const float *rv, const float *proj, float *x, float *m, float *v, int t0,
+                        int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv, int batch,
+                        void *stream)
+{
+    if (!g)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    Geom2D G;
+    int st = make_geom2d(g, false, &G);
+    if (st != PH_OK)
+        return st;
+    const size_t np = (size_t)batch * g->n_proj * g->det_shape, nimg = (size_t)batch * g->vol_shape[0] * g->vol_shape[1];
+    auto fwd = [&](const float *img, float *sino) { return ph_project_par2d(g, rv, img, sino, batch, PH_F32, stream); };
+    auto adj = [&](const float *sino, float *img) {
+        return ph_project_adjoint_par2d(g, rv, sino, img, batch, PH_F32, stream);
+    };
+    return tv_iterate(fwd, adj, 1, g->vol_shape[0], g->vol_shape[1], np, nimg, proj, x, m, v, t0, n_iter, prm, ws,
+                      ws_bytes, ph_tv_workspace_bytes_2d(g, batch), data_tv, batch, stream);
+}
+
+int ph_tv_iterate_fan2d(const ph_geom2d *g, const float *rv, const float *proj, float *x, float *m, float *v, int t0,
+                        int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv, int batch,
+                        void *stream)
+{
+    if (!g)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    Geom2D G;
+    int st = make_geom2d(g, true, &G);
+    if (st != PH_OK)
+        return st;
+    const size_t np = (size_t)batch * g->n_proj * g->det_shape, nimg = (size_t)batch * g->vol_shape[0] * g->vol_shape[1];
+    auto fwd = [&](const float *img, float *sino) { return ph_project_fan2d(g, rv, img, sino, batch, PH_F32, stream); };
+    auto adj = [&](const float *sino, float *img) {
+        return ph_project_adjoint_fan2d(g, rv, sino, img, batch, PH_F32, stream);
+    };
+    return tv_iterate(fwd, adj, 1, g->vol_shape[0], g->vol_shape[1], np, nimg, proj, x, m, v, t0, n_iter, prm, ws,
+                      ws_bytes, ph_tv_workspace_bytes_2d(g, batch), data_tv, batch, stream);
+}
+
+int ph_tv_iterate_cone3d(const ph_geom3d *g, const float *mats, const float *proj, float *x, float *m, float *v,
+                         int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv,
+                         int batch, void *stream)
+{
+    if (!g)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    Geom3D G;
+    int st = make_geom3d(g, &G);
+    if (st != PH_OK)
+        return st;
+    const size_t np = (size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1];
+    const size_t nimg = (size_t)batch * g->vol_shape[0] * g->vol_shape[1] * g->vol_shape[2];
+    auto fwd = [&](const float *vol, float *pr) { return ph_project_cone3d(g, mats, vol, pr, batch, PH_F32, stream); };
+    auto adj = [&](const float *pr, float *vol) {
+        return ph_project_adjoint_cone3d(g, mats, pr, vol, batch, PH_F32, stream);
+    };
+    return tv_iterate(fwd, adj, g->vol_shape[0], g->vol_shape[1], g->vol_shape[2], np, nimg, proj, x, m, v, t0, n_iter,
+                      prm, ws, ws_bytes, ph_tv_workspace_bytes_3d(g, batch), data_tv, batch, stream);
+}
+
 }  // extern "C"

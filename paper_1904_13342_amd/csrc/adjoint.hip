@@ -23,22 +23,26 @@ namespace {
 
 // --------------------------------------------------------------- A^T, 2D
 
-template <typename T, typename TI, bool FAN>
+// S lanes share one pixel (S a power of two, at most 64, so the lanes of a
+// pixel lie in one wave): lane s gathers views s, s + S, ... and the partial
+// sums meet in a fixed shuffle tree.
+template <typename T, typename TI, bool FAN, int S>
 __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__restrict__ views,
-                                                    const TI *__restrict__ sino, T *__restrict__ img)
+                                                    const TI *__restrict__ sino, T *__restrict__ img, long n_pix)
 {
-    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const int b = blockIdx.z;
-    if (ix >= g.nx || iy >= g.ny)
-        return;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const long q = t / S;
+    const int s = (int)(t % S);
+    if (q >= n_pix)
+        return;   // whole pixels only: the S lanes of a pixel leave together
+    const int ix = (int)(q % g.nx), iy = (int)((q / g.nx) % g.ny), b = (int)(q / ((long)g.nx * g.ny));
     const TI *sb = sino + (size_t)b * g.n_proj * g.nu;
     const float fx = (float)ix, fy = (float)iy;
     // corners of the support square (ix +- 1, iy +- 1) in world mm
     const float x0 = fmaf(fx - 1.0f, g.sx, g.ox), x1 = fmaf(fx + 1.0f, g.sx, g.ox);
     const float y0 = fmaf(fy - 1.0f, g.sy, g.oy), y1 = fmaf(fy + 1.0f, g.sy, g.oy);
     float acc = 0.0f;
-    for (int k = 0; k < g.n_proj; ++k) {
+    for (int k = s; k < g.n_proj; k += S) {
         const float2 c = views[k];
         // detector bins whose rays can cross the support: project its corners
         float smin = 3.0e38f, smax = -3.0e38f;
@@ -72,7 +76,11 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
             acc = fmaf(gv, w, acc);
         }
     }
-    store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.step * acc);
+#pragma unroll
+    for (int o = S / 2; o >= 1; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if (s == 0)
+        store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.step * acc);
 }
 
 // --------------------------------------------------------------- A^T, 3D
@@ -254,16 +262,40 @@ __global__ void __launch_bounds__(256) bpT2d_kernel(Geom2D g, const float2 *__re
     }
 }
 
+template <typename T, typename TI, bool FAN, int S>
+hipError_t fpT2d_l(const Geom2D &g, const float2 *views, const void *sino, void *img, long n_pix, hipStream_t s)
+{
+    const long blocks = (n_pix * S + 255) / 256;
+    hipLaunchKernelGGL((fpT2d_kernel<T, TI, FAN, S>), dim3((unsigned)blocks), dim3(256), 0, s, g, views,
+                       (const TI *)sino, (T *)img, n_pix);
+    return hipGetLastError();
+}
+
+template <typename T, typename TI, bool FAN>
+hipError_t fpT2d_f(const Geom2D &g, const float2 *views, const void *sino, void *img, long n_pix, hipStream_t s)
+{
+    // lanes per pixel: about 2^20 threads in all, at most one lane per view
+    int S = 1;
+    while (S < 64 && 2 * S <= g.n_proj && n_pix * S * 2 <= (1L << 20))
+        S *= 2;
+    switch (S) {
+    case 1: return fpT2d_l<T, TI, FAN, 1>(g, views, sino, img, n_pix, s);
+    case 2: return fpT2d_l<T, TI, FAN, 2>(g, views, sino, img, n_pix, s);
+    case 4: return fpT2d_l<T, TI, FAN, 4>(g, views, sino, img, n_pix, s);
+    case 8: return fpT2d_l<T, TI, FAN, 8>(g, views, sino, img, n_pix, s);
+    case 16: return fpT2d_l<T, TI, FAN, 16>(g, views, sino, img, n_pix, s);
+    case 32: return fpT2d_l<T, TI, FAN, 32>(g, views, sino, img, n_pix, s);
+    default: return fpT2d_l<T, TI, FAN, 64>(g, views, sino, img, n_pix, s);
+    }
+}
+
 template <typename T, typename TI>
 hipError_t fpT2d(bool fan, const Geom2D &g, const float2 *views, const void *sino, void *img, int batch,
                  hipStream_t s)
 {
-    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
-    if (fan)
-        hipLaunchKernelGGL((fpT2d_kernel<T, TI, true>), grid, dim3(256), 0, s, g, views, (const TI *)sino, (T *)img);
-    else
-        hipLaunchKernelGGL((fpT2d_kernel<T, TI, false>), grid, dim3(256), 0, s, g, views, (const TI *)sino, (T *)img);
-    return hipGetLastError();
+    const long n_pix = (long)g.nx * g.ny * batch;
+    return fan ? fpT2d_f<T, TI, true>(g, views, sino, img, n_pix, s)
+               : fpT2d_f<T, TI, false>(g, views, sino, img, n_pix, s);
 }
 
 template <typename T>

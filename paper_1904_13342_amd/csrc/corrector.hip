@@ -43,6 +43,8 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ x, c
         grad[i] = 2.0f * inv_n * mi * d;
         local = fmaf(d, d, local);
     }
+    if (!loss)
+        return;
     local = wave_sum(local);
     if ((threadIdx.x & 63) == 0)
         part[threadIdx.x >> 6] = local;
@@ -50,7 +52,6 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ x, c
     if (threadIdx.x == 0)   // workgroup partials meet in FP64
         unsafeAtomicAdd(loss, ((double)part[0] + part[1] + part[2] + part[3]) * (double)inv_n);
 }
-
 
 // W_red[k][j] * W_cos(i, j), the fixed part of the weight of pixel (i, j) in view k
 __device__ __forceinline__ float pixel_weight(const FilterArgs &a, int k, int i, int j)
@@ -185,9 +186,11 @@ __global__ void adam_kernel(float *__restrict__ param, const float *__restrict__
 hipError_t launch_mse(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss,
                       hipStream_t s)
 {
-    hipError_t e = fill_zero((float *)loss, 2, s);
-    if (e != hipSuccess)
-        return e;
+    if (loss) {   // no loss requested: the gradient only
+        const hipError_t e = fill_zero((float *)loss, 2, s);
+        if (e != hipSuccess)
+            return e;
+    }
     const size_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(mse_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, x, ref, mask, n,
                        1.0f / (float)n, grad, loss);

@@ -25,15 +25,22 @@ __device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float
     return true;
 }
 
-template <typename T, bool FAN>
+// S lanes share one ray (S a power of two, at most 64: the lanes of a ray lie
+// in one wave); lane s takes samples k0 + s, k0 + s + S, ... and the partial
+// sums meet in a fixed shuffle tree.  Small problems (few rays, long rays)
+// then still fill the machine.
+template <typename T, bool FAN, int S>
 __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__restrict__ views,
-                                                   const T *__restrict__ img, T *__restrict__ sino)
+                                                   const T *__restrict__ img, T *__restrict__ sino, long n_rays)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    const int b = blockIdx.z;
-    if (j >= g.nu)
-        return;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const long r = t / S;
+    const int s = (int)(t % S);
+    if (r >= n_rays)
+        return;   // whole rays only: the S lanes of a ray leave together
+    const int j = (int)(r % g.nu);
+    const int k = (int)((r / g.nu) % g.n_proj);
+    const int b = (int)(r / ((long)g.nu * g.n_proj));
     const T *im = img + (size_t)b * g.nx * g.ny;
     float X0, Y0, eX, eY;
     make_ray_2d<FAN>(g, views[k], j, X0, Y0, eX, eY);
@@ -41,7 +48,7 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
     float acc = 0.0f;
     if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && lo < hi) {
         const int k0 = (int)floorf(lo) - 1, k1 = (int)ceilf(hi) + 1;
-        for (int m = k0; m <= k1; ++m) {
+        for (int m = k0 + s; m <= k1; m += S) {
             const float fm = (float)m;
             const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0);
             const float fx = floorf(X), fy = floorf(Y);
@@ -53,7 +60,11 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
             acc += fmaf(ty, a1 - a0, a0);
         }
     }
-    store_f32(sino + ((size_t)b * g.n_proj + k) * g.nu + j, g.step * acc);
+#pragma unroll
+    for (int o = S / 2; o >= 1; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if (s == 0)
+        store_f32(sino + ((size_t)b * g.n_proj + k) * g.nu + j, g.step * acc);
 }
 
 template <typename T, typename TI, bool FAN>
@@ -94,16 +105,43 @@ __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__res
     store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.dbeta * acc);
 }
 
-template <typename T>
-hipError_t fp2d(bool fan, const Geom2D &g, const float2 *views, const void *img, void *sino, int batch,
-                hipStream_t s)
+// lanes per work item so that a launch holds about 2^20 threads
+inline int lanes_for(long items, int cap)
 {
-    dim3 grid((g.nu + 255) / 256, g.n_proj, batch);
-    if (fan)
-        hipLaunchKernelGGL((fp2d_kernel<T, true>), grid, dim3(256), 0, s, g, views, (const T *)img, (T *)sino);
-    else
-        hipLaunchKernelGGL((fp2d_kernel<T, false>), grid, dim3(256), 0, s, g, views, (const T *)img, (T *)sino);
+    int S = 1;
+    while (S < cap && items * S * 2 <= (1L << 20))
+        S *= 2;
+    return S;
+}
+
+template <typename T, bool FAN, int S>
+hipError_t fp2d_s(const Geom2D &g, const float2 *views, const void *img, void *sino, long n_rays, hipStream_t s)
+{
+    const long blocks = (n_rays * S + 255) / 256;
+    hipLaunchKernelGGL((fp2d_kernel<T, FAN, S>), dim3((unsigned)blocks), dim3(256), 0, s, g, views, (const T *)img,
+                       (T *)sino, n_rays);
     return hipGetLastError();
+}
+
+template <typename T, bool FAN>
+hipError_t fp2d_f(const Geom2D &g, const float2 *views, const void *img, void *sino, long n_rays, hipStream_t s)
+{
+    switch (lanes_for(n_rays, 64)) {
+    case 1: return fp2d_s<T, FAN, 1>(g, views, img, sino, n_rays, s);
+    case 2: return fp2d_s<T, FAN, 2>(g, views, img, sino, n_rays, s);
+    case 4: return fp2d_s<T, FAN, 4>(g, views, img, sino, n_rays, s);
+    case 8: return fp2d_s<T, FAN, 8>(g, views, img, sino, n_rays, s);
+    case 16: return fp2d_s<T, FAN, 16>(g, views, img, sino, n_rays, s);
+    case 32: return fp2d_s<T, FAN, 32>(g, views, img, sino, n_rays, s);
+    default: return fp2d_s<T, FAN, 64>(g, views, img, sino, n_rays, s);
+    }
+}
+
+template <typename T>
+hipError_t fp2d(bool fan, const Geom2D &g, const float2 *views, const void *img, void *sino, int batch, hipStream_t s)
+{
+    const long n_rays = (long)g.nu * g.n_proj * batch;
+    return fan ? fp2d_f<T, true>(g, views, img, sino, n_rays, s) : fp2d_f<T, false>(g, views, img, sino, n_rays, s);
 }
 
 template <typename T, typename TI>

@@ -8,8 +8,9 @@ output is the image itself; it is forward projected and trained on
 with Adam, starting from zero.  (Eq. 7 writes the data term as a squared
 norm; the mean only rescales lam.)  One iteration is five library calls on
 the caller's stream: the forward projection, the residual gradient, the
-matched adjoint A^T, the TV gradient added in place and the Adam step.  This
-module only owns the buffers.
+matched adjoint A^T, the TV gradient added in place and the Adam step;
+`run` issues many iterations from the library in one call.  This module
+only owns the buffers.
 """
 from __future__ import annotations
 
@@ -35,7 +36,7 @@ class TVReconstruction:
         if kind not in _PROJECT:
             raise ValueError(f"kind must be one of {sorted(_PROJECT)}")
         self.project, self.adjoint, self.dims = _PROJECT[kind]
-        self.g, self.traj, self.p = g, traj, p
+        self.kind, self.g, self.traj, self.p = kind, g, traj, p
         self.lam, self.eps, self.lr, self.betas, self.adam_eps = lam, eps, lr, betas, adam_eps
         lead = tuple(p.shape[:-self.dims])   # batch axes (the projection tail has `dims` axes)
         shape = lead + tuple(g.vol_shape)
@@ -46,6 +47,7 @@ class TVReconstruction:
         self._r = torch.empty_like(p)
         self._gr = torch.empty_like(p)
         self._gx = torch.empty_like(self.x)
+        self._ws = None
 
     def step(self):
         """One Adam step; returns (data term, TV) at the iterate before it,
@@ -60,9 +62,16 @@ class TVReconstruction:
         return data, tv
 
     def run(self, iters):
-        out = None
-        for _ in range(iters):
-            out = self.step()
+        """iters iterations in one library call (the same five steps, issued
+        without a host round trip per kernel); returns the float64 device
+        tensor [data term, TV per item] at the iterate before the last update."""
+        if self._ws is None:
+            batch = self.x.numel() // max(1, int(torch.tensor(list(self.g.vol_shape)).prod()))
+            self._ws = torch.empty(ops.tv_workspace_bytes(self.g, batch), dtype=torch.uint8, device=self.x.device)
+        b1, b2 = self.betas
+        out = ops.tv_iterate(self.kind, self.g, self.traj, self.p, self.x, self.m, self.v, self.t, iters, self.lam,
+                             self.eps, lr=self.lr, beta1=b1, beta2=b2, adam_eps=self.adam_eps, ws=self._ws)
+        self.t += iters
         return out
 
 

@@ -14,7 +14,7 @@ import math
 import numpy as np
 import torch
 
-from ._lib import Geom2D, Geom3D, PH_BF16, PH_F16, PH_F32, check, lib
+from ._lib import Geom2D, Geom3D, PH_BF16, PH_F16, PH_F32, TvParams, check, lib
 
 _DTYPES = {torch.float32: PH_F32, torch.float16: PH_F16, torch.bfloat16: PH_BF16}
 
@@ -348,6 +348,42 @@ def tv(x, eps, dims, weight=1.0, grad=None, want_value=True):
     return value, grad
 
 
+def tv_workspace_bytes(g, batch=1):
+    fn = lib().ph_tv_workspace_bytes_3d if isinstance(g, Geom3D) else lib().ph_tv_workspace_bytes_2d
+    return int(fn(ctypes.byref(g), int(batch)))
+
+
+def tv_iterate(kind, g, traj, proj, x, m, v, t0, n_iter, lam, eps, lr=1e-2, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+               ws=None, data_tv=None):
+    """n_iter iterations of the TV-regularised reconstruction in one library
+    call (x, m, v updated in place, Adam steps t0+1 .. t0+n_iter).  Returns
+    data_tv, a float64 device tensor [1 + batch]: the data term and each
+    item's TV at the iterate before the last update."""
+    fns = {"par2d": "ph_tv_iterate_par2d", "fan2d": "ph_tv_iterate_fan2d", "cone3d": "ph_tv_iterate_cone3d"}
+    if kind not in fns:
+        raise ValueError(f"kind must be one of {sorted(fns)}")
+    batch = _dev(proj, "proj", _sino_tail(g))
+    if proj.dtype != torch.float32:
+        raise ValueError("proj must be float32")
+    nimg = batch * int(torch.tensor(list(g.vol_shape)).prod())
+    for t, name in ((x, "x"), (m, "m"), (v, "v")):
+        _f32_like(t, name, nimg)
+    t = _traj(g, traj)
+    need = tv_workspace_bytes(g, batch)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=proj.device)
+    if data_tv is None:
+        data_tv = torch.empty(1 + batch, dtype=torch.float64, device=proj.device)
+    prm = TvParams(float(lam), float(eps), float(lr), float(beta1), float(beta2), float(adam_eps))
+    status = getattr(lib(), fns[kind])(ctypes.byref(g), _fptr(t), ctypes.c_void_p(proj.data_ptr()),
+                                       ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                       ctypes.c_void_p(v.data_ptr()), int(t0), int(n_iter), ctypes.byref(prm),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                       ctypes.c_void_p(data_tv.data_ptr()), batch, _stream(proj))
+    check(fns[kind], status)
+    return data_tv
+
+
 def workspace_bytes_2d(g, batch=1):
     return int(lib().ph_workspace_bytes_2d(ctypes.byref(g), int(batch)))
 
@@ -412,5 +448,5 @@ __all__ = [
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "mse_grad", "corrector_grad_3d", "adam_step", "version",
+    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "tv_workspace_bytes", "tv_iterate", "mse_grad", "corrector_grad_3d", "adam_step", "version",
 ]

@@ -108,6 +108,28 @@ def test_iteration_parity(ph, ora):
     assert ex < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["par2d", "fan2d", "cone3d"])
+def test_library_loop_matches_composed_steps(ph, ora, kind):
+    """TVReconstruction.run (the loop inside the library) gives the iterates
+    of the composed per-call steps."""
+    spec = {"par2d": SPARSE, "fan2d": synth.config("fan2d_512").with_(vol_shape=(40, 36), n_proj=24, det_shape=(90,)),
+            "cone3d": synth.config("cone3d_crop32").with_(n_proj=20)}[kind]
+    f = gc.phantom(spec)
+    p = as_f32(ora.project(spec, f))
+    g = ph.from_spec(spec)
+    traj = ph.projection_matrices_3d(g) if kind == "cone3d" else ph.ray_vectors_2d(g)
+    a = ph.TVReconstruction(kind, g, traj, to_dev(p), lam=2e-3, eps=1e-2, lr=1e-2)
+    b = ph.TVReconstruction(kind, g, traj, to_dev(p), lam=2e-3, eps=1e-2, lr=1e-2)
+    for _ in range(15):
+        data, tvv = a.step()
+    out = b.run(15)
+    say(f"[tv loop] {kind}: data {float(data):.6e} vs {float(out[0]):.6e}; x max diff "
+        f"{float((a.x - b.x).abs().max()):.3e}")
+    assert torch.allclose(a.x, b.x, rtol=1e-6, atol=1e-7)
+    assert abs(float(out[0]) - float(data)) <= 1e-6 * abs(float(data))
+    assert abs(float(out[1]) - float(tvv)) <= 1e-6 * abs(float(tvv))
+
+
 def test_sparse_view_tv_beats_fbp(ph, ora):
     spec = SPARSE
     f, p = _sparse_problem(ora, spec, seed=3)
@@ -116,12 +138,8 @@ def test_sparse_view_tv_beats_fbp(ph, ora):
     P = to_dev(p)
     fbp = to_np(ph.fbp_par2d(g, rv, P))
     it = ph.TVReconstruction("par2d", g, rv, P, lam=3e-3, eps=1e-2, lr=2e-2)
-    first = None
-    for k in range(400):
-        data, tvv = it.step()
-        if k == 0:
-            first = float(data)
-    last = float(data)
+    first = float(it.run(1)[0])
+    last = float(it.run(399)[0])
     x = to_np(it.x)
     rm = lambda a: float(np.sqrt(np.mean((a - f) ** 2)))
     say(f"[sparse TV] data term {first:.4e} -> {last:.4e}; RMSE TV {rm(x):.4e} vs FBP {rm(fbp):.4e}")
