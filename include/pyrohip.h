@@ -255,6 +255,15 @@ int ph_mse_grad(const float *x, const float *ref, const float *mask, size_t n, f
 int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *grad_q, const float *K, int M,
                          const float *W_red, const float *W, float *dK, float *dW, int batch, void *stream);
 
+/* The filter gradient of the 2D FBP network (Sec. III.B, Eq. 6: K is the
+ * only trainable layer): dL/dK as above for q = F^H K F (W_red W_cos sino),
+ * W_cos = 1 for parallel beams (fan = 0), SDD / sqrt(SDD^2 + u^2) for fan
+ * beams.  sino, grad_q: device float[batch][n_proj][nu]; K, dK: device
+ * float[M]; W_red: device float[n_proj][nu] or NULL (the default of
+ * ph_weight_filter_2d). */
+int ph_corrector_grad_2d(const ph_geom2d *g, int fan, const float *sino, const float *grad_q, const float *K, int M,
+                         const float *W_red, float *dK, int batch, void *stream);
+
 /* One Adam step (Kingma & Ba) on n parameters, in place:
  *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
  *   param -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).

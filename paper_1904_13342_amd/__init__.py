@@ -11,7 +11,7 @@ _load_lib()
 from .ops import *  # noqa: E402,F401,F403
 from .ops import __all__ as _ops_all  # noqa: E402
 from . import autograd  # noqa: E402,F401
-from .corrector import LearnedCorrector  # noqa: E402,F401
+from .corrector import LearnedCorrector, LearnedFilter2D  # noqa: E402,F401
 from .iterative import TVReconstruction  # noqa: E402,F401
 
-__all__ = list(_ops_all) + ["autograd", "LearnedCorrector", "TVReconstruction"]
+__all__ = list(_ops_all) + ["autograd", "LearnedCorrector", "LearnedFilter2D", "TVReconstruction"]

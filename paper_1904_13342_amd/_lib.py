@@ -92,6 +92,7 @@ SIGNATURES = {
     "ph_tv_iterate_cone3d": (_I, [_G3, _FP, _P, _P, _P, _P, _I, _I, ctypes.POINTER(TvParams), _P, _SZ, _P, _I, _P]),
     "ph_mse_grad": (_I, [_P, _P, _P, _SZ, _P, _P, _P]),
     "ph_corrector_grad_3d": (_I, [_G3, _P, _P, _P, _I, _P, _P, _P, _P, _I, _P]),
+    "ph_corrector_grad_2d": (_I, [_G2, _I, _P, _P, _P, _I, _P, _P, _I, _P]),
     "ph_adam_step": (_I, [_P, _P, _P, _P, _SZ, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I,
                           _P]),
 }

@@ -89,4 +89,53 @@ class LearnedCorrector:
         return loss.clone()
 
 
-__all__ = ["LearnedCorrector"]
+class LearnedFilter2D:
+    """The 2D FBP network of Sec. III.B / Eq. 6, x = B F^H K F W p, with the
+    filter K as its only trainable layer (initialised with the ramp).
+
+    g, ray_vecs : a 2D geometry and its central ray vectors; fan selects the
+    fan-beam pair (cosine weight, distance-weighted B) over the parallel one.
+    M defaults to the linear-convolution length (smallest power of two
+    >= 2 nu - 1).
+    """
+
+    def __init__(self, g, ray_vecs, fan=False, M=None, K=None, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 device="cuda"):
+        self.g, self.rv, self.fan = g, ray_vecs, bool(fan)
+        nu = g.det_shape
+        if M is None:
+            M = 16
+            while M < 2 * nu - 1:
+                M *= 2
+        tau = g.det_spacing * (g.sid / g.sdd if fan else 1.0)
+        if K is None:
+            K = ops.filter_response("ramp", M, tau)
+        self.K = K.detach().to(device=device, dtype=torch.float32).contiguous().clone()
+        self.M = self.K.numel()
+        self.tau = tau
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.mK, self.vK = torch.zeros_like(self.K), torch.zeros_like(self.K)
+        self.t = 0
+
+    def reconstruct(self, sino):
+        fbp = ops.fbp_fan2d if self.fan else ops.fbp_par2d
+        return fbp(self.g, self.rv, sino, K=self.K)
+
+    def gradients(self, sino, target, mask=None):
+        """(loss, dL/dK) of L = mean((mask (x - target))^2)."""
+        x = self.reconstruct(sino)
+        loss, gx = ops.mse_grad(x, target, mask)
+        bT = ops.backproject_adjoint_fan2d if self.fan else ops.backproject_adjoint_par2d
+        gq = bT(self.g, self.rv, gx)
+        dK = ops.corrector_grad_2d(self.g, sino, gq, self.K, self.fan)
+        return loss, dK
+
+    def step(self, sino, target, mask=None):
+        loss, dK = self.gradients(sino, target, mask)
+        self.t += 1
+        b1, b2 = self.betas
+        ops.adam_step(self.K, dK, self.mK, self.vK, self.t, lr=self.lr, beta1=b1, beta2=b2, eps=self.eps)
+        return loss
+
+
+__all__ = ["LearnedCorrector", "LearnedFilter2D"]

@@ -1022,6 +1022,28 @@ int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *gra
     return to_status(launch_corrector_grad(a, proj, grad_q, dK, dW, (hipStream_t)stream));
 }
 
+int ph_corrector_grad_2d(const ph_geom2d *g, int fan, const float *sino, const float *grad_q, const float *K, int M,
+                         const float *W_red, float *dK, int batch, void *stream)
+{
+    if (!sino || !grad_q || !K || !dK)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    Geom2D G;
+    int st = make_geom2d(g, fan != 0, &G);
+    if (st != PH_OK)
+        return st;
+    st = filter_len(K, M, g->det_shape, &M);
+    if (st != PH_OK)
+        return st;
+    FilterArgs a;
+    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+                     g->angular_range, K, M, W_red, nullptr, &a);
+    if (st != PH_OK)
+        return st;
+    return to_status(launch_corrector_grad(a, sino, grad_q, dK, nullptr, (hipStream_t)stream));
+}
+
 int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, float lr, float beta1, float beta2,
                  float eps, int t, void *stream)
 {

@@ -53,11 +53,15 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ x, c
         unsafeAtomicAdd(loss, ((double)part[0] + part[1] + part[2] + part[3]) * (double)inv_n);
 }
 
-// W_red[k][j] * W_cos(i, j), the fixed part of the weight of pixel (i, j) in view k
+// W_red[k][j] * W_cos(i, j), the fixed part of the weight of pixel (i, j) in
+// view k (no cosine weight for parallel beams, cos_sdd = 0)
 __device__ __forceinline__ float pixel_weight(const FilterArgs &a, int k, int i, int j)
 {
+    const float wr = a.W_red[(size_t)k * a.nu + j];
+    if (a.cos_sdd <= 0.0f)
+        return wr;
     const float u = ((float)j - a.cu) * a.du, v = ((float)i - a.cv) * a.dv;
-    return a.W_red[(size_t)k * a.nu + j] * a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
+    return wr * a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
 }
 
 template <int M>

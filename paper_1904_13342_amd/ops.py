@@ -306,6 +306,24 @@ def corrector_grad_3d(g, proj, grad_q, K, W_red=None, W=None, dK=None, dW=None, 
     return dK, dW
 
 
+def corrector_grad_2d(g, sino, grad_q, K, fan, W_red=None, dK=None):
+    """dL/dK of q = F^H K F (W_red W_cos sino) given dL/dq (2D FBP network)."""
+    if sino.dtype != torch.float32 or grad_q.dtype != torch.float32:
+        raise ValueError("sino and grad_q must be float32")
+    batch = _dev(sino, "sino", _sino_tail(g))
+    if grad_q.shape != sino.shape or not grad_q.is_contiguous() or grad_q.device != sino.device:
+        raise ValueError("grad_q must be a contiguous tensor of the shape of sino")
+    M = K.numel()
+    if dK is None:
+        dK = torch.empty(M, dtype=torch.float32, device=sino.device)
+    status = lib().ph_corrector_grad_2d(ctypes.byref(g), int(bool(fan)), ctypes.c_void_p(sino.data_ptr()),
+                                        ctypes.c_void_p(grad_q.data_ptr()), _f32_like(K, "K"), M,
+                                        _f32_dev(W_red, "W_red", g.n_proj * g.det_shape), _f32_like(dK, "dK", M),
+                                        batch, _stream(sino))
+    check("ph_corrector_grad_2d", status)
+    return dK
+
+
 def adam_step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One in-place Adam step (t counts from 1)."""
     n = param.numel()
@@ -448,5 +466,6 @@ __all__ = [
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "tv_workspace_bytes", "tv_iterate", "mse_grad", "corrector_grad_3d", "adam_step", "version",
+    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "tv_workspace_bytes", "tv_iterate", "mse_grad",
+    "corrector_grad_3d", "corrector_grad_2d", "adam_step", "version",
 ]

@@ -101,3 +101,28 @@ def test_adam_matches_torch_optimizer():
         opt.step()
         p, m, v = adam(p, g, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps)
         assert np.allclose(p, t_param.detach().numpy(), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["par2d", "fan2d"])
+def test_filter_gradient_2d_matches_finite_differences(ora, kind):
+    """The 2D FBP network with K as the only trainable layer (Eq. 6)."""
+    base = synth.config("par2d_64") if kind == "par2d" else synth.config("fan2d_512")
+    spec = base.with_(vol_shape=(14, 12), vol_spacing=(1.0, 1.1), det_shape=(19,), det_spacing=(1.3,), n_proj=11,
+                      sid=40.0, sdd=70.0)
+    rng = np.random.default_rng(8)
+    p = rng.standard_normal((2, spec.n_proj, 19))
+    ref = rng.standard_normal((2,) + spec.vol_shape)
+    M = 64
+    K = ora.ramp_response(M, ora.tau(spec)) + 0.1 * rng.standard_normal(M)
+
+    def loss(Kv):
+        xs = np.stack([ora.fbp(spec, p[b], K=Kv) for b in range(2)])
+        return ora.mse(xs, ref)
+
+    _, gx = loss(K)
+    gq = np.stack([ora.backproject_adjoint(spec, gx[b]) for b in range(2)])
+    dK, _ = ora.corrector_grad(spec, p, gq, K)
+    for _ in range(3):
+        d = rng.standard_normal(M)
+        fd = (loss(K + 0.5 * d)[0] - loss(K - 0.5 * d)[0]) / 1.0
+        assert abs(fd - float(dK @ d)) <= 1e-9 * abs(fd)
