@@ -39,16 +39,17 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 
 # HBM bytes per launch at 512^3 from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
 # what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524308 KiB, WRITE_SIZE 1048580 KiB).
-# A record holds for the kernel sources it was taken on (hash below); after any change the traffic is reported as null.
+# A record holds for the kernel's device sources it was taken on (hash below); after any change to them the traffic
+# is reported as null.
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.0, 1048580.0
 MEASURED_TRAFFIC = {
     "fp_cone": {"fetch_kib": 7.61368e7, "write_kib": 1.21983e6,
-                "sources": ("cone_fp.hip", "device_util.h", "common.h"), "sha256_16": "e2d3b21ec899ed78"},
+                "sources": ("cone_fp.hip", "device_util.h"), "sha256_16": "74fb9496b46fc0de"},
     "bp_cone": {"fetch_kib": 9.3219e6, "write_kib": 524288.0,
-                "sources": ("cone_bp.hip", "device_util.h", "common.h"), "sha256_16": "3c0bf9c76253fff8"},
+                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "d5b250dd331b4e04"},
     "weight_filter": {"fetch_kib": 563968.0, "write_kib": 1.10592e6,
-                      "sources": ("filter.hip", "fft.h", "common.h"), "sha256_16": "dafff71523ff20b7"},
+                      "sources": ("filter.hip", "fft.h"), "sha256_16": "7e11a0f0494e1eb3"},
 }
 
 
