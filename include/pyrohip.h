@@ -150,9 +150,9 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
  *   img/vol   : device output, same layout as the projector's input
  * ph_backproject_adjoint_*: B^T, projection_(k,i,j) = dbeta * sum_x f(x)
  * w_k(x) Lambda(j - su_k(x)) Lambda(i - sv_k(x)) with w_k = 1 (parallel) or
- * (SID/w)^2.  Scatter with float atomics: FP32 storage only (other dtypes ->
- * PH_ERR_UNSUPPORTED); summation order, hence the last bits, may vary from
- * run to run.
+ * (SID/w)^2.  Scatter with float atomics: FP32 storage here (other dtypes ->
+ * PH_ERR_UNSUPPORTED; the _ws variants below take them); summation order,
+ * hence the last bits, may vary from run to run.
  *   img/vol   : device FP32 input; sino/proj : device FP32 output */
 int ph_project_adjoint_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
                              int dtype, void *stream);
@@ -166,6 +166,19 @@ int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *ray_vecs, cons
                                  int dtype, void *stream);
 int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
                                   int dtype, void *stream);
+
+/* B^T with any storage type (extension 1): the scatter accumulates in FP32,
+ * in the output itself for FP32 and otherwise in the workspace `ws` of
+ * ph_backproject_adjoint_workspace_bytes_*() bytes (0 for FP32, where ws may
+ * be NULL), which is then rounded to the storage type (nearest even). */
+size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, int dtype);
+size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, int dtype);
+int ph_backproject_adjoint_ws_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, void *ws,
+                                    size_t ws_bytes, int batch, int dtype, void *stream);
+int ph_backproject_adjoint_ws_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, void *ws,
+                                    size_t ws_bytes, int batch, int dtype, void *stream);
+int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws,
+                                     size_t ws_bytes, int batch, int dtype, void *stream);
 
 /* --------------------------------------------- weighting + ramp filtering
  * Eq. 4 / Eq. 5 without the back-projection: q = F^H K F (W_red * W_cos * W * p),

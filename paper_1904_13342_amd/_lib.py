@@ -76,6 +76,11 @@ SIGNATURES = {
     "ph_backproject_adjoint_par2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
     "ph_backproject_adjoint_fan2d": (_I, [_G2, _FP, _P, _P, _I, _I, _P]),
     "ph_backproject_adjoint_cone3d": (_I, [_G3, _FP, _P, _P, _I, _I, _P]),
+    "ph_backproject_adjoint_workspace_bytes_2d": (_SZ, [_G2, _I, _I]),
+    "ph_backproject_adjoint_workspace_bytes_3d": (_SZ, [_G3, _I, _I]),
+    "ph_backproject_adjoint_ws_par2d": (_I, [_G2, _FP, _P, _P, _P, _SZ, _I, _I, _P]),
+    "ph_backproject_adjoint_ws_fan2d": (_I, [_G2, _FP, _P, _P, _P, _SZ, _I, _I, _P]),
+    "ph_backproject_adjoint_ws_cone3d": (_I, [_G3, _FP, _P, _P, _P, _SZ, _I, _I, _P]),
     "ph_weight_filter_2d": (_I, [_G2, _I, _P, _P, _P, _I, _P, _I, _I, _P]),
     "ph_weight_filter_3d": (_I, [_G3, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "ph_workspace_bytes_2d": (_SZ, [_G2, _I]),

@@ -437,6 +437,19 @@ const float *wred_table(int kind, int n_proj, int nu, double du, double range, d
 
 int to_status(hipError_t e) { return e == hipSuccess ? PH_OK : PH_ERR_HIP; }
 
+// Host-only validation of a 2D call's geometry and ray vectors.
+int validate2d(const ph_geom2d *g, bool fan, const float *rv)
+{
+    Geom2D G;
+    int st = make_geom2d(g, fan, &G);
+    if (st != PH_OK)
+        return st;
+    if (!rv)
+        return PH_ERR_NULL;
+    std::vector<float2> v;
+    return views2d(g, fan, rv, &v);
+}
+
 int prep2d(const ph_geom2d *g, bool fan, const float *rv, Geom2D *G, const float2 **views)
 {
     int st = make_geom2d(g, fan, G);
@@ -649,8 +662,10 @@ int fbp2d(const ph_geom2d *g, bool fan, const float *rv, const void *sino, void 
     return to_status(launch_backproject_2d(dtype, fan, G, views, q, true, img, batch, (hipStream_t)stream));
 }
 
+// B^T accumulates with float atomics: FP32 output directly, half-precision
+// output through an FP32 workspace that is then rounded to the storage type.
 int adjoint2d(const ph_geom2d *g, bool fan, bool of_projector, const float *rv, const void *in, void *out,
-              int batch, int dtype, void *stream)
+              int batch, int dtype, void *stream, void *ws = nullptr, size_t ws_bytes = 0, bool ws_call = false)
 {
     if (!in || !out)
         return PH_ERR_NULL;
@@ -659,17 +674,27 @@ int adjoint2d(const ph_geom2d *g, bool fan, bool of_projector, const float *rv, 
     int st = check_dtype(dtype);
     if (st != PH_OK)
         return st;
-    if (!of_projector && dtype != PH_F32)
+    if (!of_projector && dtype != PH_F32 && !ws_call)
         return PH_ERR_UNSUPPORTED;
     Geom2D G;
     const float2 *views = nullptr;
+    st = validate2d(g, fan, rv);
+    if (st != PH_OK)
+        return st;
+    const size_t n_out = (size_t)batch * g->n_proj * g->det_shape;
+    const bool via_ws = !of_projector && dtype != PH_F32;
+    if (via_ws && (!ws || ws_bytes < round_up(n_out * sizeof(float))))
+        return PH_ERR_WORKSPACE;
     st = prep2d(g, fan, rv, &G, &views);
     if (st != PH_OK)
         return st;
     if (of_projector)
         return to_status(launch_project_adjoint_2d(dtype, fan, G, views, in, out, batch, (hipStream_t)stream));
-    return to_status(
-        launch_backproject_adjoint_2d(fan, G, views, (const float *)in, (float *)out, batch, (hipStream_t)stream));
+    float *acc = via_ws ? (float *)ws : (float *)out;
+    st = to_status(launch_backproject_adjoint_2d(dtype, fan, G, views, in, acc, batch, (hipStream_t)stream));
+    if (st != PH_OK || !via_ws)
+        return st;
+    return to_status(launch_cast_from_f32(dtype, acc, out, n_out, (hipStream_t)stream));
 }
 
 }  // namespace
@@ -951,8 +976,8 @@ int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void 
                                                  batch, (hipStream_t)stream));
 }
 
-int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
-                                  int dtype, void *stream)
+static int bpT3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws, size_t ws_bytes,
+                 bool ws_call, int batch, int dtype, void *stream)
 {
     if (!proj || !vol)
         return PH_ERR_NULL;
@@ -961,16 +986,67 @@ int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const v
     int st = check_dtype(dtype);
     if (st != PH_OK)
         return st;
-    if (dtype != PH_F32)
+    if (dtype != PH_F32 && !ws_call)
         return PH_ERR_UNSUPPORTED;
     Geom3D G;
-    const void *views = nullptr;
-    bool axial = false;
-    st = prep3d(g, mats, true, &G, &views, &axial);
+    std::vector<double> P;
+    st = validate3d(g, mats, &G, &P);
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_adjoint_cone(G, (const ConeBPView *)views, axial, bp_segment(g),
-                                                     (const float *)vol, (float *)proj, batch, (hipStream_t)stream));
+    const size_t n_out = (size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1];
+    const bool via_ws = dtype != PH_F32;
+    if (via_ws && (!ws || ws_bytes < round_up(n_out * sizeof(float))))
+        return PH_ERR_WORKSPACE;
+    const void *views = nullptr;
+    bool axial = false;
+    st = upload3d(g, mats, P, true, &views, &axial);
+    if (st != PH_OK)
+        return st;
+    float *acc = via_ws ? (float *)ws : (float *)proj;
+    st = to_status(launch_backproject_adjoint_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), vol, acc,
+                                                   batch, (hipStream_t)stream));
+    if (st != PH_OK || !via_ws)
+        return st;
+    return to_status(launch_cast_from_f32(dtype, acc, proj, n_out, (hipStream_t)stream));
+}
+
+int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
+                                  int dtype, void *stream)
+{
+    return bpT3d(g, mats, vol, proj, nullptr, 0, false, batch, dtype, stream);
+}
+
+size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, int dtype)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1 || check_dtype(dtype) != PH_OK || dtype == PH_F32)
+        return 0;
+    return round_up((size_t)batch * g->n_proj * g->det_shape * sizeof(float));
+}
+
+size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, int dtype)
+{
+    if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1 || check_dtype(dtype) != PH_OK ||
+        dtype == PH_F32)
+        return 0;
+    return round_up((size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1] * sizeof(float));
+}
+
+int ph_backproject_adjoint_ws_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
+                                    size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
+}
+
+int ph_backproject_adjoint_ws_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
+                                    size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
+}
+
+int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws,
+                                     size_t ws_bytes, int batch, int dtype, void *stream)
+{
+    return bpT3d(g, mats, vol, proj, ws, ws_bytes, true, batch, dtype, stream);
 }
 
 int ph_filter_response(int kind, int M, double tau, float *K)

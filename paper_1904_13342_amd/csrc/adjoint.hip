@@ -310,6 +310,25 @@ hipError_t fpT_cone(const Geom3D &g, const ConeFPView *fviews, const ConeBPView 
 
 }  // namespace
 
+template <typename T>
+__global__ void cast_kernel(const float *__restrict__ in, T *__restrict__ out, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        store_f32(out + i, in[i]);
+}
+
+hipError_t launch_cast_from_f32(int dtype, const float *in, void *out, size_t n, hipStream_t s)
+{
+    const size_t blocks = (n + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 4096 ? blocks : 4096));
+    switch (dtype) {
+    case 1: hipLaunchKernelGGL(cast_kernel<f16_t>, grid, dim3(256), 0, s, in, (f16_t *)out, n); break;
+    case 2: hipLaunchKernelGGL(cast_kernel<bf16_t>, grid, dim3(256), 0, s, in, (bf16_t *)out, n); break;
+    default: hipLaunchKernelGGL(cast_kernel<float>, grid, dim3(256), 0, s, in, (float *)out, n); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t fill_zero(float *p, size_t n, hipStream_t s)
 {
     const size_t blocks = (n + 255) / 256;
@@ -338,18 +357,29 @@ hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPV
     }
 }
 
-hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
-                                         float *sino, int batch, hipStream_t stream)
+template <typename TI>
+hipError_t bpT2d(bool fan, const Geom2D &g, const float2 *views, const void *img, float *sino, int batch,
+                 hipStream_t stream)
+{
+    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
+    if (fan)
+        hipLaunchKernelGGL((bpT2d_kernel<TI, true>), grid, dim3(256), 0, stream, g, views, (const TI *)img, sino);
+    else
+        hipLaunchKernelGGL((bpT2d_kernel<TI, false>), grid, dim3(256), 0, stream, g, views, (const TI *)img, sino);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_adjoint_2d(int in_dtype, bool fan, const Geom2D &g, const float2 *views,
+                                         const void *img, float *sino, int batch, hipStream_t stream)
 {
     hipError_t e = fill_zero(sino, (size_t)batch * g.n_proj * g.nu, stream);
     if (e != hipSuccess)
         return e;
-    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
-    if (fan)
-        hipLaunchKernelGGL((bpT2d_kernel<float, true>), grid, dim3(256), 0, stream, g, views, img, sino);
-    else
-        hipLaunchKernelGGL((bpT2d_kernel<float, false>), grid, dim3(256), 0, stream, g, views, img, sino);
-    return hipGetLastError();
+    switch (in_dtype) {
+    case 0: return bpT2d<float>(fan, g, views, img, sino, batch, stream);
+    case 1: return bpT2d<f16_t>(fan, g, views, img, sino, batch, stream);
+    default: return bpT2d<bf16_t>(fan, g, views, img, sino, batch, stream);
+    }
 }
 
 }  // namespace ph

@@ -97,10 +97,12 @@ hipError_t launch_project_adjoint_2d(int dtype, bool fan, const Geom2D &g, const
 hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPView *fviews,
                                        const ConeBPView *bviews, const void *proj, void *vol, int batch,
                                        hipStream_t stream);
-hipError_t launch_backproject_adjoint_2d(bool fan, const Geom2D &g, const float2 *views, const float *img,
-                                         float *sino, int batch, hipStream_t stream);
-hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
-                                           const float *vol, float *proj, int batch, hipStream_t stream);
+hipError_t launch_backproject_adjoint_2d(int in_dtype, bool fan, const Geom2D &g, const float2 *views,
+                                         const void *img, float *sino, int batch, hipStream_t stream);
+hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views, bool axial,
+                                           int nz_seg, const void *vol, float *proj, int batch, hipStream_t stream);
+// out[i] = in[i] rounded to the storage type (nearest even)
+hipError_t launch_cast_from_f32(int dtype, const float *in, void *out, size_t n, hipStream_t stream);
 // zero-fill kernel (used in place of a memset, which would not replay
 // correctly inside a captured graph)
 hipError_t fill_zero(float *p, size_t n, hipStream_t stream);

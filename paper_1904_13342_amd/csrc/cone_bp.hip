@@ -301,9 +301,9 @@ __device__ __forceinline__ void flush_tile(const double *tile, const Footprint &
     }
 }
 
-template <int BP_NZ>
+template <typename TI, int BP_NZ>
 __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPView *__restrict__ views,
-                                                        const float *__restrict__ vol, float *__restrict__ proj,
+                                                        const TI *__restrict__ vol, float *__restrict__ proj,
                                                         int nbx, int nby, int nzb)
 {
     constexpr int ZQ = BP_NZ / 4;   // voxels in z per lane group
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
     const float cy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) : byi * 16) - hy;
     const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
 
-    const float *vb = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)z0 * g.ny * g.nx;
+    const TI *vb = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)z0 * g.ny * g.nx;
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
     float val[4][ZQ];
     int cur = -1;   // lane layout of val: 0 = lanes along y, 1 = lanes along x
@@ -341,11 +341,11 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
                 const int ix = bxi * 16 + (orient == 0 ? 4 * wave + c : a);
                 const int iy = byi * 16 + (orient == 0 ? a : 4 * wave + c);
                 const bool act = ix < g.nx && iy < g.ny;
-                const float *src = vb + (size_t)(act ? iy : 0) * g.nx + (act ? ix : 0);
+                const TI *src = vb + (size_t)(act ? iy : 0) * g.nx + (act ? ix : 0);
 #pragma unroll
                 for (int m = 0; m < ZQ; ++m) {
                     const int z = zq * ZQ + m;
-                    val[c][m] = (act && z < zcount) ? g.dbeta * src[(size_t)z * g.ny * g.nx] : 0.0f;
+                    val[c][m] = (act && z < zcount) ? g.dbeta * load_f32(src + (size_t)z * g.ny * g.nx) : 0.0f;
                 }
             }
         }
@@ -398,9 +398,9 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
 }
 
 // General projection matrices: one thread per column segment, as in B.
-template <int BP_NZ>
+template <typename TI, int BP_NZ>
 __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBPView *__restrict__ views,
-                                                          const float *__restrict__ vol, float *__restrict__ proj,
+                                                          const TI *__restrict__ vol, float *__restrict__ proj,
                                                           int nbx, int nby, int nzb)
 {
     __shared__ double tile[BP_TH * BPT_TS];
@@ -424,10 +424,10 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
     const float cz = zc0 + ((corner & 4) ? (float)(zcount - 1) : 0.0f);
 
     float val[BP_NZ];
-    const float *src = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)(active ? iy : 0) * g.nx + (active ? ix : 0);
+    const TI *src = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)(active ? iy : 0) * g.nx + (active ? ix : 0);
 #pragma unroll
     for (int z = 0; z < BP_NZ; ++z)
-        val[z] = (active && z < zcount) ? g.dbeta * src[(size_t)(z0 + z) * g.ny * g.nx] : 0.0f;
+        val[z] = (active && z < zcount) ? g.dbeta * load_f32(src + (size_t)(z0 + z) * g.ny * g.nx) : 0.0f;
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
 
     for (int k = 0; k < g.n_proj; ++k) {
@@ -507,29 +507,43 @@ hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView 
     }
 }
 
-hipError_t launch_backproject_adjoint_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
-                                           const float *vol, float *proj, int batch, hipStream_t stream)
+template <typename TI>
+hipError_t bpT_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg, const void *vol, float *proj,
+                    int batch, hipStream_t stream)
+{
+    const int NZ = nz_seg >= 32 ? 32 : 16;
+    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
+    const dim3 grid((unsigned)(nbx * nby * nzb * batch));
+    const TI *v = (const TI *)vol;
+    if (NZ == 32) {
+        if (axial)
+            hipLaunchKernelGGL((bpT_axial_kernel<TI, 32>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
+                               nzb);
+        else
+            hipLaunchKernelGGL((bpT_general_kernel<TI, 32>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
+                               nzb);
+    } else {
+        if (axial)
+            hipLaunchKernelGGL((bpT_axial_kernel<TI, 16>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
+                               nzb);
+        else
+            hipLaunchKernelGGL((bpT_general_kernel<TI, 16>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
+                               nzb);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views, bool axial,
+                                           int nz_seg, const void *vol, float *proj, int batch, hipStream_t stream)
 {
     hipError_t e = fill_zero(proj, (size_t)batch * g.n_proj * g.nv * g.nu, stream);
     if (e != hipSuccess)
         return e;
-    const int NZ = nz_seg >= 32 ? 32 : 16;
-    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
-    const dim3 grid((unsigned)(nbx * nby * nzb * batch));
-    if (NZ == 32) {
-        if (axial)
-            hipLaunchKernelGGL((bpT_axial_kernel<32>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby, nzb);
-        else
-            hipLaunchKernelGGL((bpT_general_kernel<32>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                               nzb);
-    } else {
-        if (axial)
-            hipLaunchKernelGGL((bpT_axial_kernel<16>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby, nzb);
-        else
-            hipLaunchKernelGGL((bpT_general_kernel<16>), grid, dim3(256), 0, stream, g, views, vol, proj, nbx, nby,
-                               nzb);
+    switch (in_dtype) {
+    case 0: return bpT_cone<float>(g, views, axial, nz_seg, vol, proj, batch, stream);
+    case 1: return bpT_cone<f16_t>(g, views, axial, nz_seg, vol, proj, batch, stream);
+    default: return bpT_cone<bf16_t>(g, views, axial, nz_seg, vol, proj, batch, stream);
     }
-    return hipGetLastError();
 }
 
 }  // namespace ph

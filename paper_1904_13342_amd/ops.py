@@ -196,17 +196,40 @@ def project_adjoint_cone3d(g, mats, proj, out=None):
     return _unary("ph_project_adjoint_cone3d", g, mats, proj, _sino_tail(g), _vol_tail(g), out)
 
 
+def _bpT(fn, g, traj, x, out):
+    """B^T; half-precision storage goes through the FP32-accumulating _ws entry point."""
+    if x.dtype == torch.float32:
+        return _unary(fn, g, traj, x, _vol_tail(g), _sino_tail(g), out)
+    batch = _dev(x, "input", _vol_tail(g))
+    t = _traj(g, traj)
+    shape = (tuple(x.shape[:1]) if x.dim() == len(_vol_tail(g)) + 1 else ()) + tuple(_sino_tail(g))
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError(f"out must be a contiguous {x.dtype} tensor of shape {shape} on {x.device}")
+    q = lib().ph_backproject_adjoint_workspace_bytes_3d if isinstance(g, Geom3D) else \
+        lib().ph_backproject_adjoint_workspace_bytes_2d
+    nbytes = int(q(ctypes.byref(g), batch, _DTYPES[x.dtype]))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    name = fn.replace("ph_backproject_adjoint_", "ph_backproject_adjoint_ws_")
+    status = getattr(lib(), name)(ctypes.byref(g), _fptr(t), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes, batch,
+                                  _DTYPES[x.dtype], _stream(x))
+    check(name, status)
+    return out
+
+
 def backproject_adjoint_par2d(g, ray_vecs, img, out=None):
-    """B^T of backproject_par2d (exact transpose; FP32 only)."""
-    return _unary("ph_backproject_adjoint_par2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+    """B^T of backproject_par2d (exact transpose; any storage type, FP32 accumulation)."""
+    return _bpT("ph_backproject_adjoint_par2d", g, ray_vecs, img, out)
 
 
 def backproject_adjoint_fan2d(g, ray_vecs, img, out=None):
-    return _unary("ph_backproject_adjoint_fan2d", g, ray_vecs, img, _vol_tail(g), _sino_tail(g), out)
+    return _bpT("ph_backproject_adjoint_fan2d", g, ray_vecs, img, out)
 
 
 def backproject_adjoint_cone3d(g, mats, vol, out=None):
-    return _unary("ph_backproject_adjoint_cone3d", g, mats, vol, _vol_tail(g), _sino_tail(g), out)
+    return _bpT("ph_backproject_adjoint_cone3d", g, mats, vol, out)
 
 
 def _filter_len(K, M):

@@ -71,12 +71,22 @@ def test_backproject_adjoint_parity(ph, ora, name):
     assert err < FP32_TOL
 
 
-def test_backproject_adjoint_rejects_half(ph):
+def test_backproject_adjoint_plain_entry_rejects_half(ph):
+    """The plain B^T entry point is FP32-only (its scatter accumulates in the
+    output); half precision goes through the workspace variant."""
+    import ctypes
+    from paper_1904_13342_amd._lib import lib
     spec = SPECS["cone_crop32"]
-    g, traj, _, _, _, bT = _ops(ph, spec)
-    from paper_1904_13342_amd._lib import PyroHipError
-    with pytest.raises(PyroHipError):
-        bT(g, traj, torch.zeros(spec.vol_shape, dtype=torch.float16, device=gc.device()))
+    g, traj, _, _, _, _ = _ops(ph, spec)
+    x = torch.zeros(spec.vol_shape, dtype=torch.float16, device=gc.device())
+    y = torch.zeros((spec.n_proj,) + tuple(spec.det_shape), dtype=torch.float16, device=gc.device())
+    st = lib().ph_backproject_adjoint_cone3d(ctypes.byref(g), traj.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                             ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 1, 1, None)
+    assert st == -7
+    st = lib().ph_backproject_adjoint_ws_cone3d(ctypes.byref(g), traj.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), None, 0,
+                                                1, 1, None)
+    assert st == -5
 
 
 def _dot(a, b):

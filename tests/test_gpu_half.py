@@ -116,3 +116,30 @@ def test_half_rounding_is_nearest_even(ph):
         expect = torch.tensor(float(np.float32(dbeta) * acc), dtype=torch.float32).to(dtype)
         centre = img[32, 32]
         assert centre.item() == expect.item(), (dtype, centre.item(), expect.item())
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
+@pytest.mark.parametrize("kind", ["cone3d", "fan2d", "par2d"])
+def test_adjoints_half(ph, ora, kind, dtype):
+    """A^T and B^T with half-precision storage (FP32 accumulation; B^T through
+    its workspace entry point) against the oracle's transposes on the stored
+    input."""
+    spec = {"cone3d": SPEC_3D, "fan2d": SPEC_2D, "par2d": synth.config("par2d_64")}[kind]
+    g = ph.from_spec(spec)
+    if kind == "cone3d":
+        traj, aT, bT = ph.projection_matrices_3d(g), ph.project_adjoint_cone3d, ph.backproject_adjoint_cone3d
+    else:
+        traj = ph.ray_vectors_2d(g)
+        aT = ph.project_adjoint_fan2d if kind == "fan2d" else ph.project_adjoint_par2d
+        bT = ph.backproject_adjoint_fan2d if kind == "fan2d" else ph.backproject_adjoint_par2d
+    f = gc.phantom(spec)
+    p = as_f32(ora.project(spec, f))
+    pq, fq = quantise(p, dtype), quantise(f, dtype)
+    out = aT(g, traj, to_dev(pq, dtype))
+    err = rel_l2(to_np(out), ora.project_adjoint(spec, pq))
+    say(f"[project_adjoint {kind} {dtype}] {err:.2e}")
+    assert out.dtype == dtype and err < BOUND[dtype]
+    out = bT(g, traj, to_dev(fq, dtype))
+    err = rel_l2(to_np(out), ora.backproject_adjoint(spec, fq))
+    say(f"[backproject_adjoint {kind} {dtype}] {err:.2e}")
+    assert out.dtype == dtype and err < BOUND[dtype]
