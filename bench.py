@@ -76,10 +76,12 @@ def parse():
     ap.add_argument("--config", default="cone3d_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("fdk", "corrector", "tv", "filter2d", "copyref"), default="fdk",
+    ap.add_argument("--workload", choices=("fdk", "corrector", "tv", "filter2d", "precision", "copyref"),
+                    default="fdk",
                     help="fdk: the projector / FDK hot path (default); corrector: the learned-corrector training run; "
                          "tv: sparse-view TV-regularised iterative reconstruction; "
                          "filter2d: learning the 2D reconstruction filter alone from the ramp; "
+                         "precision: FP16 / BF16 storage against FP32 at 512^3 (RMSE and speed); "
                          "copyref: one plain 1 GiB device copy, the reference that scales the HBM byte counters")
     ap.add_argument("--iters", type=int, default=500, help="tv: iterations")
     ap.add_argument("--lam", type=float, default=3e-3, help="tv: TV weight")
@@ -369,6 +371,60 @@ def filter2d_main(args):
     print(json.dumps(line), flush=True)
 
 
+def precision_main(args):
+    """FP16 and BF16 storage against FP32 on the 512^3 workload: the phantom is
+    stored in each type, forward projected and reconstructed by FDK in that
+    type (FP32 arithmetic throughout), and each reconstruction's RMSE against
+    the FP32 phantom is reported with the kernels' times."""
+    import numpy as np
+    import torch
+
+    import paper_1904_13342_amd as ph
+    import synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.config("cone3d_512")
+    g = ph.from_spec(spec)
+    mats = ph.projection_matrices_3d(g)
+    prm = synth.random_ellipsoids(spec.seed, spec.n_figures, spec.vol_shape, spec.vol_spacing)
+    vol = synth.rasterize_ellipsoids(prm, spec.vol_shape, spec.vol_spacing, sub=1, device=dev,
+                                     dtype=torch.float32).contiguous()
+    # voxels inside the inscribed cylinder (radius 128 mm), which every view
+    # covers over the full height at this magnification
+    _, ys, xs = synth.grid_axes(spec.vol_shape, spec.vol_spacing)
+    Y = torch.as_tensor(ys, device=dev).view(-1, 1)
+    X = torch.as_tensor(xs, device=dev).view(1, -1)
+    mask = (X * X + Y * Y <= 128.0 ** 2).unsqueeze(0).expand(spec.vol_shape)
+    out = {}
+    for name, dt in (("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)):
+        v = vol.to(dt).contiguous()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ph.fdk_cone3d(g, mats, ph.project_cone3d(g, mats, v))   # warm-up: per-view tables, filter tables
+        torch.cuda.synchronize()
+        ev[0].record()
+        p = ph.project_cone3d(g, mats, v)
+        ev[1].record()
+        rec = ph.fdk_cone3d(g, mats, p)
+        ev[2].record()
+        torch.cuda.synchronize()
+        d = (rec.double() - vol.double())[mask]
+        out[name] = {"rmse": float(d.pow(2).mean().sqrt()), "fp_ms": ev[0].elapsed_time(ev[1]),
+                     "fdk_ms": ev[1].elapsed_time(ev[2]),
+                     "bytes": {"volume": v.numel() * v.element_size(), "projections": p.numel() * p.element_size()}}
+        del p, rec, v
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "FDK reconstruction RMSE and time with FP16 / BF16 storage vs FP32 (FP32 arithmetic)",
+        "value": out["f16"]["rmse"] / out["f32"]["rmse"], "unit": "RMSE ratio f16/f32", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f32 arithmetic; f32/f16/bf16 storage",
+        "data": "synthetic: 12 seeded random ellipsoids",
+        "config": {"workload": "cone3d 512^3 at 0.5 mm, 360 views over 360 deg, 1024x768 detector at 0.8 mm",
+                   "rmse_region": "inscribed cylinder r <= 128 mm, all slices"},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -383,6 +439,9 @@ def main():
         return
     if args.workload == "filter2d":
         filter2d_main(args)
+        return
+    if args.workload == "precision":
+        precision_main(args)
         return
     if args.workload == "copyref":
         import torch
