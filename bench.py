@@ -189,7 +189,9 @@ def corrector_main(args):
     every step adds fresh Gaussian noise and takes one Adam step on K (M taps,
     ramp initialisation) and W (ones).  Held-out seeds 1000-1003 (noise drawn
     once) give the RMSE of the learned reconstruction, of the ramp
-    initialisation and of plain Ram-Lak / Parker FDK."""
+    initialisation, of plain Ram-Lak / Parker FDK and of Ram-Lak sampled on
+    the learned filter's grid, over the whole volume and over the covered
+    cylinder (r <= 128 mm, |z| < 124 mm)."""
     import numpy as np
     import torch
 
@@ -217,12 +219,27 @@ def corrector_main(args):
     torch.cuda.synchronize()
     print(f"[corrector] data ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    def rmse(x):
-        return float(((x.double() - x_test.double()) ** 2).mean().sqrt())
+    # inscribed cylinder (r <= 128 mm) over the slices every view covers (|z| < 124 mm)
+    zs, ys, xs = synth.grid_axes(spec.vol_shape, spec.vol_spacing)
+    Zc = torch.as_tensor(zs, device=dev).view(-1, 1, 1)
+    Yc = torch.as_tensor(ys, device=dev).view(1, -1, 1)
+    Xc = torch.as_tensor(xs, device=dev).view(1, 1, -1)
+    fov = ((Xc * Xc + Yc * Yc <= 128.0 ** 2) & (Zc.abs() < 124.0)).expand(tuple(spec.vol_shape))
+
+    def rmse(x, region=None):
+        d = (x.double() - x_test.double()) ** 2
+        if region is not None:
+            d = d[:, region]
+        return float(d.mean().sqrt())
 
     corr = ph.LearnedCorrector(g, mats, M=args.taps, lr=args.lr)
-    rmse_init = rmse(corr.reconstruct(p_test))
-    rmse_plain = rmse(ph.fdk_cone3d(g, mats, p_test))
+    x_init = corr.reconstruct(p_test)
+    x_plain = ph.fdk_cone3d(g, mats, p_test)
+    tau = spec.det_spacing[1] * spec.sid / spec.sdd
+    x_rl = ph.fdk_cone3d(g, mats, p_test, K=ph.filter_response("ramlak", args.taps, tau).to(dev))
+    rmse_init, rmse_plain, rmse_rl = rmse(x_init), rmse(x_plain), rmse(x_rl)
+    fov_init, fov_plain, fov_rl = rmse(x_init, fov), rmse(x_plain, fov), rmse(x_rl, fov)
+    del x_init, x_plain, x_rl
     noisy = torch.empty_like(p_train)
     noise = torch.empty_like(p_train)
     losses = []
@@ -242,7 +259,8 @@ def corrector_main(args):
     torch.cuda.synchronize()
     ms = [a.elapsed_time(b) for a, b in step_ms]
     losses = [float(v) for v in losses]
-    rmse_learned = rmse(corr.reconstruct(p_test))
+    x_learned = corr.reconstruct(p_test)
+    rmse_learned, fov_learned = rmse(x_learned), rmse(x_learned, fov)
     line = {
         "metric": "learned-corrector training steps/s (FDK + MSE + B^T + K/W gradients + Adam)",
         "value": 1e3 / float(np.mean(ms[1:] if len(ms) > 1 else ms)),
@@ -257,7 +275,10 @@ def corrector_main(args):
         "ms_per_step": float(np.mean(ms[1:] if len(ms) > 1 else ms)),
         "loss_first": losses[0],
         "loss_last10": float(np.mean(losses[-10:])),
-        "rmse_heldout": {"learned": rmse_learned, "ramp_init": rmse_init, "plain_ramlak_parker_fdk": rmse_plain},
+        "rmse_heldout": {"learned": rmse_learned, "ramp_init": rmse_init, "plain_ramlak_parker_fdk": rmse_plain,
+                         "ramlak_on_the_learned_grid": rmse_rl},
+        "rmse_heldout_covered_cylinder": {"learned": fov_learned, "ramp_init": fov_init,
+                                          "plain_ramlak_parker_fdk": fov_plain, "ramlak_on_the_learned_grid": fov_rl},
     }
     if args.save:
         np.savez(args.save, K=corr.K.cpu().numpy(), W=corr.W.cpu().numpy(), losses=np.array(losses),
