@@ -396,7 +396,8 @@ def precision_main(args):
     """FP16 and BF16 storage against FP32 on the 512^3 workload: the phantom is
     stored in each type, forward projected and reconstructed by FDK in that
     type (FP32 arithmetic throughout), and each reconstruction's RMSE against
-    the FP32 phantom is reported with the kernels' times."""
+    the FP32 phantom is reported with the kernels' times (median of three
+    repetitions into preallocated outputs)."""
     import numpy as np
     import torch
 
@@ -417,22 +418,31 @@ def precision_main(args):
     X = torch.as_tensor(xs, device=dev).view(1, -1)
     mask = (X * X + Y * Y <= 128.0 ** 2).unsqueeze(0).expand(spec.vol_shape)
     out = {}
+    reps = 3
+    nbytes = ph.workspace_bytes_3d(g, 1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     for name, dt in (("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)):
         v = vol.to(dt).contiguous()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ph.fdk_cone3d(g, mats, ph.project_cone3d(g, mats, v))   # warm-up: per-view tables, filter tables
+        p = torch.empty((spec.n_proj,) + tuple(spec.det_shape), dtype=dt, device=dev)
+        rec = torch.empty(tuple(spec.vol_shape), dtype=dt, device=dev)
+        ph.fdk_cone3d(g, mats, ph.project_cone3d(g, mats, v, out=p), out=rec, ws=ws)   # warm-up
         torch.cuda.synchronize()
-        ev[0].record()
-        p = ph.project_cone3d(g, mats, v)
-        ev[1].record()
-        rec = ph.fdk_cone3d(g, mats, p)
-        ev[2].record()
-        torch.cuda.synchronize()
+        fp_ms, fdk_ms = [], []
+        for _ in range(reps):     # outputs and workspace preallocated: only the kernels are timed
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            ph.project_cone3d(g, mats, v, out=p)
+            ev[1].record()
+            ph.fdk_cone3d(g, mats, p, out=rec, ws=ws)
+            ev[2].record()
+            torch.cuda.synchronize()
+            fp_ms.append(ev[0].elapsed_time(ev[1]))
+            fdk_ms.append(ev[1].elapsed_time(ev[2]))
         d = (rec.double() - vol.double())[mask]
-        out[name] = {"rmse": float(d.pow(2).mean().sqrt()), "fp_ms": ev[0].elapsed_time(ev[1]),
-                     "fdk_ms": ev[1].elapsed_time(ev[2]),
+        out[name] = {"rmse": float(d.pow(2).mean().sqrt()), "fp_ms": sorted(fp_ms)[reps // 2],
+                     "fdk_ms": sorted(fdk_ms)[reps // 2],
                      "bytes": {"volume": v.numel() * v.element_size(), "projections": p.numel() * p.element_size()}}
-        del p, rec, v
+        del p, rec, v, d
         torch.cuda.empty_cache()
     line = {
         "metric": "FDK reconstruction RMSE and time with FP16 / BF16 storage vs FP32 (FP32 arithmetic)",

@@ -291,6 +291,8 @@ int bp_segment(const ph_geom3d *g)
 void fp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeFPView> *out)
 {
     const double cu = 0.5 * (g->det_shape[1] - 1), cv = 0.5 * (g->det_shape[0] - 1);
+    const float step = (float)default_step(
+        g->step_mm, std::fmin(g->vol_spacing[0], std::fmin(g->vol_spacing[1], g->vol_spacing[2])));
     out->resize((size_t)g->n_proj);
     for (int k = 0; k < g->n_proj; ++k) {
         const double *m = &P[12 * (size_t)k];
@@ -312,6 +314,10 @@ void fp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
             v.d0[r] = d0[r];
             v.du[r] = du[r];
             v.dv[r] = dv[r];
+            // the FP32 spacing and step the kernels see; x, y, z order
+            const double sp = (double)(float)g->vol_spacing[2 - r];
+            v.inv_sp[r] = 1.0 / sp;
+            v.step_sp[r] = (double)step / sp;
         }
     }
 }

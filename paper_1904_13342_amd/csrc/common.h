@@ -74,6 +74,8 @@ struct ConeFPView {
     double d0[3];
     double du[3];
     double dv[3];
+    double inv_sp[3];    // 1 / voxel spacing (x, y, z)
+    double step_sp[3];   // sampling step / voxel spacing (x, y, z)
 };
 
 // ------------------------------------------------------------------ launchers

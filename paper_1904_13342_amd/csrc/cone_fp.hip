@@ -5,16 +5,15 @@
 // interpolated trilinearly with zero outside the grid.
 //
 // Mapping: a workgroup owns a 16 x 16 detector tile of one view.  Its rays
-// form a thin pyramid from the source, and all of them travel mostly along one
-// horizontal axis A (x or y, the larger component of the view's central ray).
-// The volume is walked in slabs of D planes across A; for each slab the
-// cross-section of the pyramid (bounded by the tile's four corner rays, plus a
-// one-voxel margin, clipped to the grid and a two-voxel zero halo) is staged
-// in LDS, and every ray then takes the samples whose floor(A coordinate)
-// falls in the slab, with all eight trilinear corners read from LDS.  A sample
-// belongs to exactly one slab, decided by the same FP32 coordinate the
-// interpolation uses.  Slabs that do not fit in LDS, and tiles whose rays do
-// not share a dominant axis, read the volume directly.
+// form a thin pyramid from the source and all advance along one horizontal
+// axis A (x or y, chosen per tile from its corner rays).  The volume is walked
+// in slabs of D planes across A; for each slab the cross-section of the
+// pyramid (bounded by the tile's four corner rays, plus a one-voxel margin,
+// clipped to the grid and a two-voxel zero halo) is staged in LDS, and every
+// ray then takes the samples whose floor(A coordinate) falls in the slab,
+// with all eight trilinear corners read from LDS.  A sample belongs to
+// exactly one slab, decided by the same FP32 coordinate the interpolation
+// uses.  Slabs that do not fit in LDS read the volume directly.
 #include "device_util.h"
 
 namespace ph {
@@ -23,10 +22,11 @@ namespace {
 constexpr int FP_TILE = 16;            // detector tile edge (pixels)
 constexpr int FP_D = 8;                // slab depth (planes along A)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
-constexpr int FP_LDS_FLOATS = 9984;    // 39 KiB slab capacity: four workgroups per CU
+constexpr int FP_LDS_FLOATS = 9728;    // 38 KiB slab capacity (with the boxes: four workgroups per CU)
 constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
 constexpr int FP_VG = 8;               // views of one tile scheduled together
 constexpr int FP_XCDS = 8;             // accelerator complex dies, each with its own L2
+constexpr int FP_BOXES = 64;           // slab cross-sections computed per batch
 
 template <typename T>
 __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix, int iy, int iz)
@@ -34,6 +34,25 @@ __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix,
     return ((unsigned)ix < (unsigned)nx && (unsigned)iy < (unsigned)ny && (unsigned)iz < (unsigned)nz)
                ? load_f32(f + ((size_t)iz * ny + iy) * nx + ix)
                : 0.0f;
+}
+
+// Raw buffer reads of the slab staging: the descriptor holds the base of a
+// run of z planes (word 3 is the gfx9 raw-buffer format), the lane's byte
+// offset within a plane goes in a VGPR and the plane's byte offset in an SGPR,
+// so a load costs no vector address arithmetic.  Every offset used stays
+// below the descriptor's record count.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_run(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s);
+template <> __device__ __forceinline__ float buf_f32<f16_t>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s)
+{
+    return (float)__builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
+}
+template <> __device__ __forceinline__ float buf_f32<bf16_t>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s)
+{
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0) << 16);
 }
 
 __device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float &hi)
@@ -94,8 +113,8 @@ __device__ __forceinline__ float sample_lds(const float *slab, int m, float PA0,
 // Slab walk of one tile along the dominant axis AX (0: x, 1: y); B is the
 // other horizontal axis, C = z.  LDS layout [c][b][a], a fastest.
 template <typename T, int AX>
-__device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *slab, int *s_range, const Ray &r,
-                                           const Ray cr[4], bool hit, int kb, int ke)
+__device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *slab, int *s_range, int4 *s_box,
+                                           const Ray &r, const Ray cr[4], bool hit, int kb, int ke)
 {
     constexpr int BX = 1 - AX;
     const int tid = threadIdx.x;
@@ -128,34 +147,92 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
 
     float acc = 0.0f;
     int m = kb;   // next sample of this ray
-    for (int n = 0; n <= s_max - s_min; ++n) {
+    const int n_slabs = s_max - s_min + 1;
+    for (int n = 0; n < n_slabs; ++n) {
         const int s = sgn > 0.0f ? s_min + n : s_max - n;
         const int a0 = -2 + s * FP_D;   // first plane of the slab
-        // cross-section of the tile's pyramid between planes a0 and a0 + D
-        float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
+        if (n % FP_BOXES == 0) {
+            // cross-sections of the tile's pyramid between planes a0 and a0 + D
+            // for the next FP_BOXES slabs, one slab per thread: the corner rays
+            // clipped to the grid plus a two-voxel halo (one more cell below,
+            // two above the floor of the extreme coordinates)
+            __syncthreads();   // the previous batch has been read
+            for (int u = tid; u < min(FP_BOXES, n_slabs - n); u += 256) {
+                const int su = sgn > 0.0f ? s + u : s - u;
+                const int au = -2 + su * FP_D;
+                float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < 4; ++c) {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const float t = ((float)(a0 + e * FP_D) - cr[c].p[AX]) * rA[c];
-                const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
-                bmin = fminf(bmin, bb);
-                bmax = fmaxf(bmax, bb);
-                cmin = fminf(cmin, cc);
-                cmax = fmaxf(cmax, cc);
+                    for (int e = 0; e < 2; ++e) {
+                        const float t = ((float)(au + e * FP_D) - cr[c].p[AX]) * rA[c];
+                        const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
+                        bmin = fminf(bmin, bb);
+                        bmax = fmaxf(bmax, bb);
+                        cmin = fminf(cmin, cc);
+                        cmax = fmaxf(cmax, cc);
+                    }
+                }
+                s_box[u] = make_int4(max((int)floorf(bmin) - 1, -2), min((int)floorf(bmax) + 2, NB + 1),
+                                     max((int)floorf(cmin) - 1, -2), min((int)floorf(cmax) + 2, NC + 1));
             }
+            __syncthreads();
         }
-        const int b_lo = max((int)floorf(bmin) - 1, -2), b_hi = min((int)floorf(bmax) + 2, NB + 1);
-        const int c_lo = max((int)floorf(cmin) - 1, -2), c_hi = min((int)floorf(cmax) + 2, NC + 1);
+        const int4 box = s_box[n % FP_BOXES];
+        const int b_lo = box.x, b_hi = box.y, c_lo = box.z, c_hi = box.w;
         const int HB = b_hi - b_lo + 1, HC = c_hi - c_lo + 1;
         const bool staged = HB > 0 && HC > 0 && FP_WA * HB * HC <= FP_LDS_FLOATS;
         if (staged) {
             __syncthreads();   // the previous slab has been consumed
             // each thread owns fixed (a, b) cells of the slab and walks them up
             // through the z planes; rows along x (the fastest axis in memory)
-            // keep the loads coalesced
-            const int L = AX == 0 ? FP_WA : HB;   // x-run length
+            // keep the loads coalesced.  Planes outside the grid are zero; the
+            // rest are read through buffer descriptors over runs of eight planes
+            // (plane offsets are uniform, the cell's byte offset is per lane).
             const int plane = FP_WA * HB;         // cells per z plane
+            const int z_lo = max(c_lo, 0), z_hi = min(c_hi, NC - 1);
+            const int n_below = min(z_lo - c_lo, HC), n_in = max(z_hi - z_lo + 1, 0);   // n_below + n_in <= HC
+            const size_t zstride = (size_t)g.nx * g.ny;
+            const unsigned zbytes = (unsigned)(zstride * sizeof(T));
+            const T *fz = f + (size_t)z_lo * zstride;
+            if constexpr (sizeof(T) == 4) {
+                // FP32: the loads write LDS directly (cell q of a plane is
+                // LDS word q, so a wave fills 64 consecutive words per plane);
+                // every load of the slab is in flight at once and one wait
+                // ends the staging.  Columns outside the grid are zeroed.
+                for (int q = tid; q < plane; q += 256) {
+                    const int ib = q / FP_WA, ia = q - ib * FP_WA;
+                    const int ga = a0 + ia, gb = b_lo + ib;
+                    const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
+                    const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
+                    float *dst = slab + q;
+                    for (int ic = 0; ic < n_below; ++ic)
+                        dst[ic * plane] = 0.0f;
+                    for (int ic = n_below + n_in; ic < HC; ++ic)
+                        dst[ic * plane] = 0.0f;
+                    if (in_xy) {
+                        const unsigned xy = (unsigned)(gy * g.nx + gx) * 4u;
+                        // first word of this wave's run of 64 cells
+                        float *wrun = slab + __builtin_amdgcn_readfirstlane(q & ~63);
+                        const T *src = fz;
+                        for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
+                            const int cnt = min(n_in - ic0, 8);
+                            const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
+                            float *wd = wrun + (n_below + ic0) * plane;
+                            for (int u = 0; u < cnt; ++u)
+                                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                    rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
+                                    (unsigned)u * zbytes, 0, 0);
+                            src += 8 * zstride;
+                        }
+                    } else {
+                        for (int ic = n_below; ic < n_below + n_in; ++ic)
+                            dst[ic * plane] = 0.0f;
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);   // the loads have landed in LDS
+            } else {
+            const int L = AX == 0 ? FP_WA : HB;   // x-run length
             const float invL = 1.0f / (float)L;
             for (int q = tid; q < plane; q += 256) {
                 int row = (int)(((float)q + 0.5f) * invL);   // quotient, corrected to exact
@@ -166,26 +243,36 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
                 const int ga = a0 + ia, gb = b_lo + ib;
                 const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
                 const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
-                const T *src = f + (size_t)(in_xy ? gy : 0) * g.nx + (in_xy ? gx : 0);
+                const unsigned xy = in_xy ? (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T) : 0u;
                 float *dst = slab + ib * FP_WA + ia;
-                const size_t zstride = (size_t)g.nx * g.ny;
-                // eight z planes at a time: the loads are unconditional (from
-                // a valid address) and issue back to back, the out-of-grid
-                // ones are zeroed afterwards
-                for (int ic0 = 0; ic0 < HC; ic0 += 8) {
+                for (int ic = 0; ic < n_below; ++ic)
+                    dst[ic * plane] = 0.0f;
+                float *d = dst + n_below * plane;
+                const T *src = fz;
+                int left = n_in;
+                // eight planes at a time: the loads issue back to back
+                for (; left >= 8; left -= 8) {
+                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, 8u * zbytes);
                     float vals[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int gz = c_lo + ic0 + u;
-                        const bool ok = in_xy && ic0 + u < HC && (unsigned)gz < (unsigned)g.nz;
-                        const float val = load_f32(src + (ok ? (size_t)gz * zstride : (size_t)0));
-                        vals[u] = ok ? val : 0.0f;
-                    }
+                    for (int u = 0; u < 8; ++u)
+                        vals[u] = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
-                        if (ic0 + u < HC)
-                            dst[(ic0 + u) * plane] = vals[u];
+                        d[u * plane] = in_xy ? vals[u] : 0.0f;
+                    src += 8 * zstride;
+                    d += 8 * plane;
                 }
+                if (left > 0) {
+                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)left * zbytes);
+                    for (int u = 0; u < left; ++u) {
+                        const float val = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
+                        d[u * plane] = in_xy ? val : 0.0f;
+                    }
+                }
+                for (int ic = n_below + n_in; ic < HC; ++ic)
+                    dst[ic * plane] = 0.0f;
+            }
             }
             __syncthreads();
         }
@@ -245,6 +332,8 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
                                                       const T *__restrict__ vol, T *__restrict__ proj, FpWork wk)
 {
     __shared__ float slab[FP_LDS_FLOATS];
+    __shared__ int4 s_box[FP_BOXES];
+    __shared__ Ray s_corner[4];
     __shared__ int s_range[2];
     const int tid = threadIdx.x;
     const unsigned per_xcd = gridDim.x / FP_XCDS;
@@ -268,23 +357,46 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     // one sample of margin on each side; samples outside the box add zeros
     const int kb = hit ? (int)floorf(lo) : 0, ke = hit ? (int)ceilf(hi) : -1;
 
-    // the tile's four corner rays bound the pyramid of its rays
+    // the tile's four corner rays bound the pyramid of its rays; they are the
+    // rays of the threads owning the corner pixels (always valid pixels), so
+    // those threads publish theirs instead of every thread setting up four
+    // more rays in double precision
     const int jh = min(j0 + FP_TILE - 1, g.nu - 1), ih = min(i0 + FP_TILE - 1, g.nv - 1);
+    {
+        const int tj = tid % FP_TILE, ti = tid / FP_TILE;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (tj == ((c & 1) ? jh - j0 : 0) && ti == ((c & 2) ? ih - i0 : 0))
+                s_corner[c] = r;
+    }
+    __syncthreads();
     Ray cr[4];
-    cr[0] = make_cone_ray(g, v, j0, i0);
-    cr[1] = make_cone_ray(g, v, jh, i0);
-    cr[2] = make_cone_ray(g, v, j0, ih);
-    cr[3] = make_cone_ray(g, v, jh, ih);
-    const int ax = fabs(v.d0[0]) >= fabs(v.d0[1]) ? 0 : 1;
-    // every ray must advance along A in one direction, at least as fast as
-    // across it, and by at most one voxel per step (margin samples stay
-    // inside the two-voxel halo)
-    bool slab_ok = g.step <= fminf(g.sx, fminf(g.sy, g.sz));
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        cr[c] = s_corner[c];
+    // slab axis A of this tile: the horizontal axis along which its slowest
+    // corner ray still advances fastest (the rays of a tile span a fraction of
+    // a degree, so near 45 degrees one tile walks x and its neighbour y).
+    // The walk needs every ray to advance along A in one direction (interior
+    // rays are positive combinations of the corner directions) and by at
+    // most one voxel per step on every axis (margin samples stay inside the
+    // two-voxel halo); the cross-section may grow faster than one voxel per
+    // plane, in which case a slab that outgrows LDS reads the volume
+    // directly.  A run of eight planes must also fit a buffer descriptor's
+    // 32-bit range.
+    float mx = 3.0e38f, my = 3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        mx = fminf(mx, fabsf(cr[c].e[0]));
+        my = fminf(my, fabsf(cr[c].e[1]));
+    }
+    const int ax = mx >= my ? 0 : 1;
+    bool slab_ok = g.step <= fminf(g.sx, fminf(g.sy, g.sz)) && (size_t)g.nx * g.ny * sizeof(T) * 8 <= 0xffffffffu;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const float eA = cr[c].e[ax], eB = cr[c].e[1 - ax];
-        slab_ok = slab_ok && eA * cr[0].e[ax] > 0.0f && fabsf(eA) >= fabsf(eB) && fabsf(eA) >= fabsf(cr[c].e[2]) &&
-                  fabsf(eA) <= 1.0f && fabsf(eB) <= 1.0f && fabsf(cr[c].e[2]) <= 1.0f;
+        slab_ok = slab_ok && eA * cr[0].e[ax] > 0.0f && fabsf(eA) <= 1.0f && fabsf(eB) <= 1.0f &&
+                  fabsf(cr[c].e[2]) <= 1.0f;
     }
 
     float acc = 0.0f;
@@ -294,9 +406,9 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
             acc += sample_global(f, g, ray_coord_biased(P0, r.e[0], m) - RAY_BIAS,
                                  ray_coord_biased(P1, r.e[1], m) - RAY_BIAS, ray_coord_biased(P2, r.e[2], m) - RAY_BIAS);
     } else if (ax == 0) {
-        acc = slab_walk<T, 0>(g, f, slab, s_range, r, cr, hit, kb, ke);
+        acc = slab_walk<T, 0>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
     } else {
-        acc = slab_walk<T, 1>(g, f, slab, s_range, r, cr, hit, kb, ke);
+        acc = slab_walk<T, 1>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
     }
     if (valid)
         store_f32(proj + (((size_t)b * g.n_proj + k) * g.nv + i) * g.nu + j, g.step * acc);

@@ -13,7 +13,10 @@ struct Ray {
 
 // Ray of cone-beam detector pixel (j, i), set up in double precision (the
 // source is ~SID away, so an FP32 direction would misplace the ray by
-// ~SID * 2^-24 at the volume) and rounded once to FP32.  The forward
+// ~SID * 2^-24 at the volume) and rounded once to FP32.  The direction is
+// normalised with the hardware reciprocal square root refined by two Newton
+// steps, and the per-view reciprocals of the spacing replace divisions, so
+// the set-up takes a few dozen double-precision operations.  The forward
 // projector and its transpose both use this, so they see the same samples.
 __device__ __forceinline__ Ray make_cone_ray(const Geom3D &g, const ConeFPView &v, int j, int i)
 {
@@ -22,17 +25,21 @@ __device__ __forceinline__ Ray make_cone_ray(const Geom3D &g, const ConeFPView &
 #pragma unroll
     for (int t = 0; t < 3; ++t)
         d[t] = fma(jc, v.du[t], fma(ic, v.dv[t], v.d0[t]));
-    const double rn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double n2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
+    const double h = 0.5 * n2;
+    double rn = __builtin_amdgcn_rsq(n2);
+    rn = rn * fma(-h * rn, rn, 1.5);
+    rn = rn * fma(-h * rn, rn, 1.5);
 #pragma unroll
     for (int t = 0; t < 3; ++t)
         d[t] *= rn;
     const double t0 = -(v.s[0] * d[0] + v.s[1] * d[1] + v.s[2] * d[2]);
-    const double o[3] = {g.ox, g.oy, g.oz}, s[3] = {g.sx, g.sy, g.sz};
+    const double o[3] = {g.ox, g.oy, g.oz};
     Ray r;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-        r.p[t] = (float)((fma(t0, d[t], v.s[t]) - o[t]) / s[t]);
-        r.e[t] = (float)((double)g.step * d[t] / s[t]);
+        r.p[t] = (float)((fma(t0, d[t], v.s[t]) - o[t]) * v.inv_sp[t]);
+        r.e[t] = (float)(d[t] * v.step_sp[t]);
     }
     return r;
 }
