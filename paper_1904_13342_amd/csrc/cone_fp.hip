@@ -20,13 +20,14 @@ namespace ph {
 namespace {
 
 constexpr int FP_TILE = 16;            // detector tile edge (pixels)
-constexpr int FP_D = 8;                // slab depth (planes along A)
+constexpr int FP_D = 6;                // slab depth (planes along A; D + 1 odd keeps LDS rows off shared banks)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
-constexpr int FP_LDS_FLOATS = 9728;    // 38 KiB slab capacity (with the boxes: four workgroups per CU)
+constexpr int FP_LDS_FLOATS = 7680;    // 30 KiB slab capacity (with the boxes: five workgroups per CU)
+constexpr int FP_HALF = FP_LDS_FLOATS / 2;   // one buffer of the double-buffered pair
 constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
 constexpr int FP_VG = 8;               // views of one tile scheduled together
 constexpr int FP_XCDS = 8;             // accelerator complex dies, each with its own L2
-constexpr int FP_BOXES = 64;           // slab cross-sections computed per batch
+constexpr int FP_BOXES = 32;           // slab cross-sections computed per batch (ring of two batches)
 
 template <typename T>
 __device__ __forceinline__ float vox(const T *f, int nx, int ny, int nz, int ix, int iy, int iz)
@@ -91,23 +92,121 @@ __device__ __forceinline__ bool in_slab(int m, float eA, float PA0, int offA)
     return (unsigned)((int)fmaf((float)m, eA, PA0) - offA) < (unsigned)FP_D;
 }
 
-// Trilinear sample m from the LDS slab ([c][b][a], a fastest; biased
-// coordinates are positive, so truncation is floor).
-__device__ __forceinline__ float sample_lds(const float *slab, int m, float PA0, float eA, float PB0, float eB,
-                                            float PC0, float eC, int HB, int base, int sb, int sc)
+// Trilinear sample at (float) index fm from the LDS slab ([c][b][a], a
+// fastest).  Biased coordinates are positive, so truncation is floor; the
+// cell's byte offset is formed with 24-bit multiplies (every factor is below
+// 2^24), and `base` folds the slab's offsets in (bytes, modulo 2^32).
+__device__ __forceinline__ float sample_lds(const float *slab, float fm, float PA0, float eA, float PB0, float eB,
+                                            float PC0, float eC, unsigned base, unsigned sc)
 {
-    const float fm = (float)m;
     const float A = fmaf(fm, eA, PA0), B = fmaf(fm, eB, PB0), C = fmaf(fm, eC, PC0);
-    const int iA = (int)A, iB = (int)B, iC = (int)C;
+    const unsigned iA = (unsigned)A, iB = (unsigned)B, iC = (unsigned)C;
     const float tA = __builtin_amdgcn_fractf(A), tB = __builtin_amdgcn_fractf(B), tC = __builtin_amdgcn_fractf(C);
-    const int cell = __mul24(__mul24(iC, HB) + iB, FP_WA) + iA + base;
-    const float *p = slab + cell;
+    const unsigned off = __umul24(iC, 4u * sc) + __umul24(iB, 4u * FP_WA) + (iA << 2) + base;   // bytes
+    const float *p = (const float *)((const char *)slab + off);
+    constexpr int sb = FP_WA;
     const float l00 = fmaf(tA, p[1] - p[0], p[0]);
     const float l10 = fmaf(tA, p[sb + 1] - p[sb], p[sb]);
     const float l01 = fmaf(tA, p[sc + 1] - p[sc], p[sc]);
     const float l11 = fmaf(tA, p[sc + sb + 1] - p[sc + sb], p[sc + sb]);
     const float m0 = fmaf(tB, l10 - l00, l00), m1 = fmaf(tB, l11 - l01, l01);
     return fmaf(tC, m1 - m0, m0);
+}
+
+// Stage one slab (cross-section box b_lo.., c_lo.. of HB x HC cells, planes
+// a0 .. a0 + D along A) into LDS at buf, layout [c][b][a].  Each thread owns
+// fixed (a, b) cells and walks them up through the z planes.  Planes outside
+// the grid are zero; the rest are read through buffer descriptors over runs
+// of eight planes (plane offsets are uniform, the cell's byte offset is per
+// lane).  FP32 loads write LDS directly and are still in flight on return
+// (the caller waits); other storage types are converted through registers.
+template <typename T, int AX>
+__device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *buf, int a0, int b_lo, int c_lo, int HB,
+                                           int HC, int tid)
+{
+    const int plane = FP_WA * HB;   // cells per z plane
+    const int z_lo = max(c_lo, 0), z_hi = min(c_lo + HC - 1, g.nz - 1);
+    const int n_below = min(z_lo - c_lo, HC), n_in = max(z_hi - z_lo + 1, 0);   // n_below + n_in <= HC
+    const size_t zstride = (size_t)g.nx * g.ny;
+    const unsigned zbytes = (unsigned)(zstride * sizeof(T));
+    const T *fz = f + (size_t)z_lo * zstride;
+    if constexpr (sizeof(T) == 4) {
+        // cell q of a plane is LDS word q, so a wave fills 64 consecutive
+        // words per plane; columns outside the grid are zeroed
+        for (int q = tid; q < plane; q += 256) {
+            const int ib = q / FP_WA, ia = q - ib * FP_WA;
+            const int ga = a0 + ia, gb = b_lo + ib;
+            const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
+            const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
+            float *dst = buf + q;
+            for (int ic = 0; ic < n_below; ++ic)
+                dst[ic * plane] = 0.0f;
+            for (int ic = n_below + n_in; ic < HC; ++ic)
+                dst[ic * plane] = 0.0f;
+            if (in_xy) {
+                const unsigned xy = (unsigned)(gy * g.nx + gx) * 4u;
+                // first word of this wave's run of 64 cells
+                float *wrun = buf + __builtin_amdgcn_readfirstlane(q & ~63);
+                const T *src = fz;
+                for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
+                    const int cnt = min(n_in - ic0, 8);
+                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
+                    float *wd = wrun + (n_below + ic0) * plane;
+                    for (int u = 0; u < cnt; ++u)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
+                            (unsigned)u * zbytes, 0, 0);
+                    src += 8 * zstride;
+                }
+            } else {
+                for (int ic = n_below; ic < n_below + n_in; ++ic)
+                    dst[ic * plane] = 0.0f;
+            }
+        }
+    } else {
+        // rows along x (the fastest axis in memory) keep the loads coalesced
+        const int L = AX == 0 ? FP_WA : HB;   // x-run length
+        const float invL = 1.0f / (float)L;
+        for (int q = tid; q < plane; q += 256) {
+            int row = (int)(((float)q + 0.5f) * invL);   // quotient, corrected to exact
+            int col = q - row * L;
+            row += (col >= L) - (col < 0);
+            col = q - row * L;
+            const int ia = AX == 0 ? col : row, ib = AX == 0 ? row : col;
+            const int ga = a0 + ia, gb = b_lo + ib;
+            const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
+            const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
+            const unsigned xy = in_xy ? (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T) : 0u;
+            float *dst = buf + ib * FP_WA + ia;
+            for (int ic = 0; ic < n_below; ++ic)
+                dst[ic * plane] = 0.0f;
+            float *d = dst + n_below * plane;
+            const T *src = fz;
+            int left = n_in;
+            // eight planes at a time: the loads issue back to back
+            for (; left >= 8; left -= 8) {
+                const __amdgpu_buffer_rsrc_t rs = plane_run(src, 8u * zbytes);
+                float vals[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    vals[u] = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    d[u * plane] = in_xy ? vals[u] : 0.0f;
+                src += 8 * zstride;
+                d += 8 * plane;
+            }
+            if (left > 0) {
+                const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)left * zbytes);
+                for (int u = 0; u < left; ++u) {
+                    const float val = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
+                    d[u * plane] = in_xy ? val : 0.0f;
+                }
+            }
+            for (int ic = n_below + n_in; ic < HC; ++ic)
+                dst[ic * plane] = 0.0f;
+        }
+    }
 }
 
 // Slab walk of one tile along the dominant axis AX (0: x, 1: y); B is the
@@ -148,133 +247,73 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
     float acc = 0.0f;
     int m = kb;   // next sample of this ray
     const int n_slabs = s_max - s_min + 1;
+    // cross-sections of the tile's pyramid between planes a0 and a0 + D of
+    // slabs n0 .. n0 + FP_BOXES - 1, one slab per thread: the corner rays
+    // clipped to the grid plus a two-voxel halo (one more cell below, two
+    // above the floor of the extreme coordinates); a ring of two batches, so
+    // the next slab's box is known while the current one is sampled
+    auto fill_boxes = [&](int n0) {
+        for (int u = tid; u < min(FP_BOXES, n_slabs - n0); u += 256) {
+            const int su = sgn > 0.0f ? s_min + n0 + u : s_max - n0 - u;
+            const int au = -2 + su * FP_D;
+            float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float t = ((float)(au + e * FP_D) - cr[c].p[AX]) * rA[c];
+                    const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
+                    bmin = fminf(bmin, bb);
+                    bmax = fmaxf(bmax, bb);
+                    cmin = fminf(cmin, cc);
+                    cmax = fmaxf(cmax, cc);
+                }
+            }
+            s_box[(n0 + u) % (2 * FP_BOXES)] =
+                make_int4(max((int)floorf(bmin) - 1, -2), min((int)floorf(bmax) + 2, NB + 1),
+                          max((int)floorf(cmin) - 1, -2), min((int)floorf(cmax) + 2, NC + 1));
+        }
+    };
+    if (n_slabs > 0) {
+        fill_boxes(0);
+        __syncthreads();
+    }
+    bool in_flight = false;   // the current slab was loaded during the previous one (uniform)
     for (int n = 0; n < n_slabs; ++n) {
         const int s = sgn > 0.0f ? s_min + n : s_max - n;
         const int a0 = -2 + s * FP_D;   // first plane of the slab
-        if (n % FP_BOXES == 0) {
-            // cross-sections of the tile's pyramid between planes a0 and a0 + D
-            // for the next FP_BOXES slabs, one slab per thread: the corner rays
-            // clipped to the grid plus a two-voxel halo (one more cell below,
-            // two above the floor of the extreme coordinates)
-            __syncthreads();   // the previous batch has been read
-            for (int u = tid; u < min(FP_BOXES, n_slabs - n); u += 256) {
-                const int su = sgn > 0.0f ? s + u : s - u;
-                const int au = -2 + su * FP_D;
-                float bmin = 3.0e38f, bmax = -3.0e38f, cmin = 3.0e38f, cmax = -3.0e38f;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const float t = ((float)(au + e * FP_D) - cr[c].p[AX]) * rA[c];
-                        const float bb = fmaf(t, cr[c].e[BX], cr[c].p[BX]), cc = fmaf(t, cr[c].e[2], cr[c].p[2]);
-                        bmin = fminf(bmin, bb);
-                        bmax = fmaxf(bmax, bb);
-                        cmin = fminf(cmin, cc);
-                        cmax = fmaxf(cmax, cc);
-                    }
-                }
-                s_box[u] = make_int4(max((int)floorf(bmin) - 1, -2), min((int)floorf(bmax) + 2, NB + 1),
-                                     max((int)floorf(cmin) - 1, -2), min((int)floorf(cmax) + 2, NC + 1));
-            }
-            __syncthreads();
-        }
-        const int4 box = s_box[n % FP_BOXES];
+        const int4 box = s_box[n % (2 * FP_BOXES)];
         const int b_lo = box.x, b_hi = box.y, c_lo = box.z, c_hi = box.w;
         const int HB = b_hi - b_lo + 1, HC = c_hi - c_lo + 1;
         const bool staged = HB > 0 && HC > 0 && FP_WA * HB * HC <= FP_LDS_FLOATS;
-        if (staged) {
-            __syncthreads();   // the previous slab has been consumed
-            // each thread owns fixed (a, b) cells of the slab and walks them up
-            // through the z planes; rows along x (the fastest axis in memory)
-            // keep the loads coalesced.  Planes outside the grid are zero; the
-            // rest are read through buffer descriptors over runs of eight planes
-            // (plane offsets are uniform, the cell's byte offset is per lane).
-            const int plane = FP_WA * HB;         // cells per z plane
-            const int z_lo = max(c_lo, 0), z_hi = min(c_hi, NC - 1);
-            const int n_below = min(z_lo - c_lo, HC), n_in = max(z_hi - z_lo + 1, 0);   // n_below + n_in <= HC
-            const size_t zstride = (size_t)g.nx * g.ny;
-            const unsigned zbytes = (unsigned)(zstride * sizeof(T));
-            const T *fz = f + (size_t)z_lo * zstride;
-            if constexpr (sizeof(T) == 4) {
-                // FP32: the loads write LDS directly (cell q of a plane is
-                // LDS word q, so a wave fills 64 consecutive words per plane);
-                // every load of the slab is in flight at once and one wait
-                // ends the staging.  Columns outside the grid are zeroed.
-                for (int q = tid; q < plane; q += 256) {
-                    const int ib = q / FP_WA, ia = q - ib * FP_WA;
-                    const int ga = a0 + ia, gb = b_lo + ib;
-                    const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
-                    const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
-                    float *dst = slab + q;
-                    for (int ic = 0; ic < n_below; ++ic)
-                        dst[ic * plane] = 0.0f;
-                    for (int ic = n_below + n_in; ic < HC; ++ic)
-                        dst[ic * plane] = 0.0f;
-                    if (in_xy) {
-                        const unsigned xy = (unsigned)(gy * g.nx + gx) * 4u;
-                        // first word of this wave's run of 64 cells
-                        float *wrun = slab + __builtin_amdgcn_readfirstlane(q & ~63);
-                        const T *src = fz;
-                        for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
-                            const int cnt = min(n_in - ic0, 8);
-                            const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
-                            float *wd = wrun + (n_below + ic0) * plane;
-                            for (int u = 0; u < cnt; ++u)
-                                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                    rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
-                                    (unsigned)u * zbytes, 0, 0);
-                            src += 8 * zstride;
-                        }
-                    } else {
-                        for (int ic = n_below; ic < n_below + n_in; ++ic)
-                            dst[ic * plane] = 0.0f;
-                    }
-                }
-                __builtin_amdgcn_s_waitcnt(0);   // the loads have landed in LDS
-            } else {
-            const int L = AX == 0 ? FP_WA : HB;   // x-run length
-            const float invL = 1.0f / (float)L;
-            for (int q = tid; q < plane; q += 256) {
-                int row = (int)(((float)q + 0.5f) * invL);   // quotient, corrected to exact
-                int col = q - row * L;
-                row += (col >= L) - (col < 0);
-                col = q - row * L;
-                const int ia = AX == 0 ? col : row, ib = AX == 0 ? row : col;
-                const int ga = a0 + ia, gb = b_lo + ib;
-                const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
-                const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
-                const unsigned xy = in_xy ? (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T) : 0u;
-                float *dst = slab + ib * FP_WA + ia;
-                for (int ic = 0; ic < n_below; ++ic)
-                    dst[ic * plane] = 0.0f;
-                float *d = dst + n_below * plane;
-                const T *src = fz;
-                int left = n_in;
-                // eight planes at a time: the loads issue back to back
-                for (; left >= 8; left -= 8) {
-                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, 8u * zbytes);
-                    float vals[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        vals[u] = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        d[u * plane] = in_xy ? vals[u] : 0.0f;
-                    src += 8 * zstride;
-                    d += 8 * plane;
-                }
-                if (left > 0) {
-                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)left * zbytes);
-                    for (int u = 0; u < left; ++u) {
-                        const float val = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
-                        d[u * plane] = in_xy ? val : 0.0f;
-                    }
-                }
-                for (int ic = n_below + n_in; ic < HC; ++ic)
-                    dst[ic * plane] = 0.0f;
-            }
-            }
+        // FP32 slabs that fit one half of the buffer are double-buffered:
+        // slab n + 1 is loaded into the other half while slab n is sampled
+        const bool small = sizeof(T) == 4 && staged && FP_WA * HB * HC <= FP_HALF;
+        float *buf = small ? slab + (n & 1) * FP_HALF : slab;
+        if (in_flight) {
+            __builtin_amdgcn_s_waitcnt(0);   // this slab's loads have landed in LDS
             __syncthreads();
+        } else if (staged) {
+            __syncthreads();   // the previous slab has been consumed
+            stage_slab<T, AX>(g, f, buf, a0, b_lo, c_lo, HB, HC, tid);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        in_flight = false;
+        if (n + 1 < n_slabs) {
+            if ((n + 1) % FP_BOXES == 0) {
+                fill_boxes(n + 1);
+                __syncthreads();
+            }
+            const int4 nb = s_box[(n + 1) % (2 * FP_BOXES)];
+            const int nHB = nb.y - nb.x + 1, nHC = nb.w - nb.z + 1;
+            // every wave has passed this iteration's barrier, so the other
+            // half (slab n - 1) is free
+            if (small && nHB > 0 && nHC > 0 && FP_WA * nHB * nHC <= FP_HALF) {
+                const int ns = sgn > 0.0f ? s + 1 : s - 1;
+                stage_slab<T, AX>(g, f, slab + ((n + 1) & 1) * FP_HALF, -2 + ns * FP_D, nb.x, nb.z, nHB, nHC, tid);
+                in_flight = true;
+            }
         }
         if (!hit)
             continue;
@@ -292,17 +331,20 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
                 ++m_end;
         }
         if (staged) {
-            // LDS cell of biased coordinates (A, B, C), as a dword index
-            const int base = -(offC * HB + offB) * FP_WA - offA;
-            const int sb = FP_WA, sc = FP_WA * HB;
-            for (; m + 1 < m_end; m += 2) {
-                acc += sample_lds(slab, m, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
-                acc += sample_lds(slab, m + 1, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
+            // LDS cell of biased coordinates (A, B, C), as a byte offset
+            const unsigned base = 4u * (unsigned)(-(offC * HB + offB) * FP_WA - offA);
+            const unsigned sc = (unsigned)(FP_WA * HB);
+            // two samples per pass (sample indices are exact in FP32); an odd
+            // last pass repeats the final sample and drops it, so a wave
+            // runs ceil(n / 2) passes for the longest lane's n samples
+            const float fend = (float)m_end;
+            for (float fm = (float)m; fm < fend; fm += 2.0f) {
+                acc += sample_lds(buf, fm, PA0, eA, PB0, eB, PC0, eC, base, sc);
+                const float f1 = fm + 1.0f;
+                const float s1 = sample_lds(buf, fminf(f1, fend - 1.0f), PA0, eA, PB0, eB, PC0, eC, base, sc);
+                acc += f1 < fend ? s1 : 0.0f;
             }
-            if (m < m_end) {
-                acc += sample_lds(slab, m, PA0, eA, PB0, eB, PC0, eC, HB, base, sb, sc);
-                ++m;
-            }
+            m = m_end;
         } else {
             for (; m < m_end; ++m) {
                 const float fm = (float)m;
@@ -332,7 +374,7 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
                                                       const T *__restrict__ vol, T *__restrict__ proj, FpWork wk)
 {
     __shared__ float slab[FP_LDS_FLOATS];
-    __shared__ int4 s_box[FP_BOXES];
+    __shared__ int4 s_box[2 * FP_BOXES];
     __shared__ Ray s_corner[4];
     __shared__ int s_range[2];
     const int tid = threadIdx.x;
