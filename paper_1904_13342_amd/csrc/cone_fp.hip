@@ -152,10 +152,12 @@ __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *b
                     const int cnt = min(n_in - ic0, 8);
                     const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
                     float *wd = wrun + (n_below + ic0) * plane;
-                    for (int u = 0; u < cnt; ++u)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
-                            (unsigned)u * zbytes, 0, 0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (u < cnt)   // uniform
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
+                                (unsigned)u * zbytes, 0, 0);
                     src += 8 * zstride;
                 }
             } else {
@@ -325,8 +327,12 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
             const float bound = sgn > 0.0f ? (float)(offA + FP_D) : (float)offA;
             const float est = (bound - fmaf((float)m, eA, PA0)) * rEA;
             m_end = min(m + max((int)ceilf(est), 1), ke + 1);
+            // the estimate is off by at most a step, so the corrections run
+            // once or not at all: keep them scalar loops
+#pragma clang loop unroll(disable) vectorize(disable) interleave(disable)
             while (m_end > m + 1 && !in_slab(m_end - 1, eA, PA0, offA))
                 --m_end;
+#pragma clang loop unroll(disable) vectorize(disable) interleave(disable)
             while (m_end <= ke && in_slab(m_end, eA, PA0, offA))
                 ++m_end;
         }
