@@ -44,11 +44,11 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.0, 1048580.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.61368e7, "write_kib": 1.21983e6,
-                "sources": ("cone_fp.hip", "device_util.h"), "sha256_16": "74fb9496b46fc0de"},
-    "bp_cone": {"fetch_kib": 9.3219e6, "write_kib": 524288.0,
-                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "d5b250dd331b4e04"},
-    "weight_filter": {"fetch_kib": 563968.0, "write_kib": 1.10592e6,
+    "fp_cone": {"fetch_kib": 7.31512e7, "write_kib": 1.23798e6,
+                "sources": ("cone_fp.hip", "device_util.h"), "sha256_16": "8d52d927e5727959"},
+    "bp_cone": {"fetch_kib": 9.14544e6, "write_kib": 524288.0,
+                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "415d1a9a6c987c52"},
+    "weight_filter": {"fetch_kib": 563930.0, "write_kib": 1.10592e6,
                       "sources": ("filter.hip", "fft.h"), "sha256_16": "7e11a0f0494e1eb3"},
 }
 
