@@ -57,7 +57,7 @@ class _Geom(ctypes.Structure):
     ]
 
 
-_KIND = {"par2d": 0, "fan2d": 1, "cone3d": 2}
+_KIND = {"par2d": 0, "fan2d": 1, "cone3d": 2, "fan2d_curved": 3}
 _lib = None
 
 
@@ -79,6 +79,8 @@ def _load():
             "ora_circular_filter": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]),
             "ora_ramlak_response": (None, [ctypes.c_int, ctypes.c_double, dp]),
             "ora_ramp_response": (None, [ctypes.c_int, ctypes.c_double, dp]),
+            "ora_equiangular_filter": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]),
+            "ora_equiangular_response": (None, [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]),
             "ora_cosine_weights": (None, [gp, dp]),
             "ora_parker": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
             "ora_redundancy_weights": (None, [gp, dp]),
@@ -196,9 +198,15 @@ def backproject_adjoint(spec, f):
 # -------------------------------------------------------------------- filters
 
 def tau(spec):
-    """Iso-scaled detector sample spacing of the ramp filter."""
+    """Iso-scaled detector sample spacing of the ramp filter (for the curved
+    fan detector: the angular pitch du/SDD times SID)."""
     du = spec.det_spacing[-1]
     return du if spec.kind == "par2d" else du * spec.sid / spec.sdd
+
+
+def fan_angle_pitch(spec):
+    """Angular pitch alpha = du / SDD of the curved (equiangular) detector."""
+    return spec.det_spacing[-1] / spec.sdd
 
 
 def fft_size(nu):
@@ -235,6 +243,21 @@ def ramlak_response(M, t):
 def ramp_response(M, t):
     K = np.empty(M)
     _load().ora_ramp_response(M, float(t), _dp(K))
+    return K
+
+
+def equiangular_filter(rows, alpha, sid):
+    """Equiangular Ram-Lak filtering of rows sampled at fan-angle pitch alpha."""
+    rows = np.ascontiguousarray(rows, dtype=np.float64)
+    nu = rows.shape[-1]
+    out = np.empty_like(rows)
+    _load().ora_equiangular_filter(rows.size // nu, nu, float(alpha), float(sid), _dp(rows), _dp(out))
+    return out
+
+
+def equiangular_response(M, alpha, sid):
+    K = np.empty(M)
+    _load().ora_equiangular_response(M, float(alpha), float(sid), _dp(K))
     return K
 
 
@@ -279,10 +302,13 @@ def weight(spec, p, W_red=None, W=None):
 
 
 def filter_projections(spec, p, K=None):
-    """Row-wise ramp filtering: Ram-Lak as a direct linear convolution when
-    ``K`` is None, otherwise the circular filter with response ``K``."""
+    """Row-wise ramp filtering: Ram-Lak (equiangular Ram-Lak on the curved
+    fan detector) as a direct linear convolution when ``K`` is None,
+    otherwise the circular filter with response ``K``."""
     p3 = np.asarray(p, dtype=np.float64).reshape(_proj_shape(spec))
     if K is None:
+        if spec.kind == "fan2d_curved":
+            return equiangular_filter(p3, fan_angle_pitch(spec), spec.sid)
         return ramlak_filter(p3, tau(spec))
     return circular_filter(p3, K)
 
@@ -413,6 +439,7 @@ def tv_grad(x, eps):
 __all__ = [
     "build", "geom", "num_threads", "project", "project_adjoint", "count_samples", "backproject",
     "backproject_adjoint", "tau", "fft_size", "ramlak_filter", "circular_filter", "ramlak_response",
-    "ramp_response", "cosine_weights", "redundancy_weights", "parker", "projection_matrices", "weight",
+    "ramp_response", "fan_angle_pitch", "equiangular_filter", "equiangular_response", "cosine_weights",
+    "redundancy_weights", "parker", "projection_matrices", "weight",
     "filter_projections", "fbp", "mse", "corrector_grad", "corrector_forward", "adam", "tv", "tv_grad",
 ]

@@ -18,7 +18,11 @@
  *   - detector pixel (i,j) (row i, column j) centre u_j = (j-(nu-1)/2)*du,
  *     v_i = (i-(nv-1)/2)*dv;
  *   - parallel: ray through u_j*e_u with direction c;
- *   - fan / cone: source S = -SID*c, flat detector centred at (SDD-SID)*c.
+ *   - fan / cone: source S = -SID*c, flat detector centred at (SDD-SID)*c;
+ *   - curved fan (equiangular detector, Kak & Slaney's equiangular rays): the
+ *     detector is the arc of radius SDD about the source, column j at fan
+ *     angle gamma_j = (j-(nu-1)/2)*du/SDD from the central ray (du is the
+ *     arc length between columns), direction cos(g)*c + sin(g)*e_u.
  * 2D geometries are the nz = 1, z = 0 special case of the same code: with
  * z = 0 the trilinear interpolation below reduces exactly to bilinear.
  *
@@ -33,7 +37,8 @@
 #endif
 
 typedef struct {
-    int kind;          /* 0 parallel 2D, 1 fan 2D (flat detector), 2 circular cone 3D */
+    int kind;          /* 0 parallel 2D, 1 fan 2D (flat detector), 2 circular cone 3D,
+                          3 fan 2D (curved equiangular detector) */
     int nx, ny, nz;    /* grid size; nz = 1 in 2D */
     double sx, sy, sz; /* voxel spacing, mm */
     double ox, oy, oz; /* world position of the centre of voxel (0,0,0), mm */
@@ -89,6 +94,12 @@ static void ray_of(const ora_geom *g, int k, int i, int j, double a[3], double d
         p[t] = (g->sdd - g->sid) * c[t] + u * eu[t];
     }
     p[2] += v;
+    if (g->kind == 3) {
+        /* the column's point on the arc of radius SDD about the source */
+        double gam = u / g->sdd;
+        for (int t = 0; t < 3; ++t)
+            p[t] = s[t] + g->sdd * (cos(gam) * c[t] + sin(gam) * eu[t]);
+    }
     double n = 0.0;
     for (int t = 0; t < 3; ++t) {
         d[t] = p[t] - s[t];
@@ -315,7 +326,9 @@ long long ora_count_samples(const ora_geom *g, const int *views, int nviews)
 /* Detector coordinates of world point x in view k: column coordinate su, row
  * coordinate sv, and the distance weight.  Parallel: orthogonal projection,
  * weight 1.  Fan / cone: central projection from the source, weight
- * (SID / w)^2 with w = depth of x along the central ray from the source. */
+ * (SID / w)^2 with w = depth of x along the central ray from the source.
+ * Curved fan: the column of the fan angle of x, weight (SID / L)^2 with L the
+ * distance of x from the source (Kak & Slaney's equiangular back-projection). */
 static void project_point(const ora_geom *g, int k, const double x[3], double *su, double *sv, double *wt)
 {
     double c[3], eu[3];
@@ -328,6 +341,14 @@ static void project_point(const ora_geom *g, int k, const double x[3], double *s
         return;
     }
     double w = x[0] * c[0] + x[1] * c[1] + g->sid;
+    if (g->kind == 3) {
+        /* fan angle of the ray through x, and 1/L^2 weighting (L = distance
+         * from the source) written as (SID/L)^2 */
+        *su = atan2(xu, w) * g->sdd / g->du + 0.5 * (g->nu - 1);
+        *sv = 0.0;
+        *wt = g->sid * g->sid / (w * w + xu * xu);
+        return;
+    }
     *su = g->sdd * xu / w / g->du + 0.5 * (g->nu - 1);
     *sv = (g->kind == 2) ? g->sdd * x[2] / w / g->dv + 0.5 * (g->nv - 1) : 0.0;
     *wt = (g->sid / w) * (g->sid / w);
@@ -477,17 +498,71 @@ void ora_ramp_response(int M, double tau, double *K)
     }
 }
 
+/* Equiangular Ram-Lak taps (Kak & Slaney, equiangular rays): the ramp kernel
+ * h of the fan angle times (gamma / sin gamma)^2, sampled at gamma = n*alpha,
+ * with the equiangular pre-weight's SID and the quadrature step alpha folded
+ * in (the 1/2 of a full turn is the redundancy weight):
+ *   t(0) = 1 / (4 alpha SID),  t(n even) = 0,
+ *   t(n odd) = -alpha / (pi^2 SID sin^2(n alpha)).
+ * For small alpha these tend to the flat taps tau * h_tau(n), tau = alpha SID. */
+static double equiangular_tap(long n, double alpha, double sid)
+{
+    if (n == 0)
+        return 1.0 / (4.0 * alpha * sid);
+    if (n % 2 == 0)
+        return 0.0;
+    double sn = sin((double)n * alpha);
+    return -alpha / (M_PI * M_PI * sid * sn * sn);
+}
+
+/* Row-wise equiangular filtering as a direct linear convolution:
+ * out(j) = sum_m t(j - m) in(m). */
+void ora_equiangular_filter(int rows, int nu, double alpha, double sid, const double *in, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < rows; ++r) {
+        const double *x = in + (size_t)r * nu;
+        double *y = out + (size_t)r * nu;
+        for (int j = 0; j < nu; ++j) {
+            double acc = 0.0;
+            for (int m = 0; m < nu; ++m)
+                acc += equiangular_tap((long)j - m, alpha, sid) * x[m];
+            y[j] = acc;
+        }
+    }
+}
+
+/* Frequency response of the equiangular taps on the M-point grid (taps
+ * wrapped M-periodically, as for the Ram-Lak response). */
+void ora_equiangular_response(int M, double alpha, double sid, double *K)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < M; ++k) {
+        double acc = 0.0;
+        for (int n = 0; n < M; ++n) {
+            long nn = n <= M / 2 ? n : n - M;
+            long kn = ((long)k * n) % M;
+            acc += equiangular_tap(nn, alpha, sid) * cos(2.0 * M_PI * (double)kn / (double)M);
+        }
+        K[k] = acc;
+    }
+}
+
 /* ---------------------------------------------------------------- weights */
 
 /* Cosine weights (Kak & Slaney), Sec. II.C.5 / Eq. 5 W_cos:
- * SDD / sqrt(SDD^2 + u^2 + v^2); identically 1 for parallel beams. */
+ * SDD / sqrt(SDD^2 + u^2 + v^2); cos(gamma_j) on the curved detector (the
+ * factor SID of the equiangular pre-weight sits in the filter taps);
+ * identically 1 for parallel beams. */
 void ora_cosine_weights(const ora_geom *g, double *wc)
 {
     for (int i = 0; i < g->nv; ++i)
         for (int j = 0; j < g->nu; ++j) {
             double u = ((double)j - 0.5 * (g->nu - 1)) * g->du;
             double v = ((double)i - 0.5 * (g->nv - 1)) * g->dv;
-            if (g->kind == 2 || g->kind == 1) {
+            if (g->kind == 3) {
+                wc[(size_t)i * g->nu + j] = cos(u / g->sdd);
+            } else if (g->kind == 2 || g->kind == 1) {
                 if (g->kind == 1)
                     v = 0.0;
                 wc[(size_t)i * g->nu + j] = g->sdd / sqrt(g->sdd * g->sdd + u * u + v * v);
@@ -532,7 +607,7 @@ void ora_redundancy_weights(const ora_geom *g, double *wr)
                 w = 0.5;
             else {
                 double u = ((double)j - 0.5 * (g->nu - 1)) * g->du;
-                w = ora_parker(beta, atan(u / g->sdd), delta);
+                w = ora_parker(beta, g->kind == 3 ? u / g->sdd : atan(u / g->sdd), delta);
             }
             wr[(size_t)k * g->nu + j] = w;
         }

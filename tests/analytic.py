@@ -4,7 +4,8 @@ Written independently of ``oracle/oracle.c``: the rays are constructed here
 from the geometry conventions (view angle beta_k = k * range / n_proj counter-
 clockwise, central ray c = (cos b, sin b, 0), detector axis e_u = (-sin b,
 cos b, 0), e_v = +z, centred detector, source at -SID c, flat detector centred
-at (SDD - SID) c), and the line integrals of ellipses, ellipsoids and Gaussian
+at (SDD - SID) c; the curved fan detector is the arc of radius SDD about the
+source, column u at fan angle u / SDD), and the line integrals of ellipses, ellipsoids and Gaussian
 blobs are the textbook chord-length / Gaussian formulas.
 """
 import math
@@ -39,6 +40,11 @@ def rays(spec, views=None):
     if spec.kind == "par2d":
         return U[..., None] * eu, c
     src = -spec.sid * c
+    if spec.kind == "fan2d_curved":
+        # equiangular detector: column u sits at fan angle u / SDD on the arc
+        # of radius SDD about the source
+        gam = U / spec.sdd
+        return src, np.cos(gam)[..., None] * c + np.sin(gam)[..., None] * eu
     det = (spec.sdd - spec.sid) * c + U[..., None] * eu + V[..., None] * ez
     d = det - src
     d /= np.linalg.norm(d, axis=-1, keepdims=True)
