@@ -73,6 +73,10 @@ typedef struct {
     float angular_range;    /* rad; view k nominally at k*range/n_proj */
     float sid, sdd;         /* mm; ignored by the parallel-beam calls */
     float step_mm;          /* ray sampling step of the forward projector; <= 0 -> half the smallest spacing */
+    int fan_detector;       /* fan calls: 0 flat, equispaced detector (bin u_j = (j-(nu-1)/2)*du on the line
+                               SDD from the source); 1 equiangular arc of radius SDD about the source, bin j
+                               at fan angle gamma_j = (j-(nu-1)/2)*du/SDD (du the arc length between bins;
+                               requires nu*du/SDD < pi).  Ignored by the parallel-beam calls. */
 } ph_geom2d;
 
 typedef struct {
@@ -128,7 +132,10 @@ int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, vo
  * interpolated linearly (2D) / bilinearly (3D) with zero outside the
  * detector; the sum is multiplied by dbeta = range/n_proj and, for fan and
  * cone beams, each term by the distance weight (SID/w)^2, w the depth of the
- * voxel along the central ray.  Same arrays as the forward calls with the
+ * voxel along the central ray.  On the equiangular fan detector
+ * (fan_detector = 1) the pixel is read at the bin of its fan angle and
+ * weighted by (SID/L)^2, L its distance from the source (Kak & Slaney's
+ * equiangular reconstruction).  Same arrays as the forward calls with the
  * roles of input and output exchanged. */
 int ph_backproject_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
                          int dtype, void *stream);
@@ -208,11 +215,24 @@ int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *ou
  * for fan and cone beams).  K: host float[M]; M a power of two in [2, 4096],
  * tau > 0 and finite. */
 int ph_filter_response(int kind, int M, double tau, float *K);
+/* Equiangular Ram-Lak response for the curved fan detector (Kak & Slaney,
+ * equiangular rays): the DFT on the M-point grid of the taps t(0) =
+ * 1/(4 alpha SID), t(n odd) = -alpha / (pi^2 SID sin^2(n alpha)), t(n even)
+ * = 0 for |n| <= M/2 (the ramp kernel of the fan angle times
+ * (gamma/sin gamma)^2, with the pre-weight's SID and the step alpha folded
+ * in).  alpha = du/SDD is the angular pitch of the bins.  Host only.
+ * K: host float[M]; M a power of two in [2, 4096]; alpha in (0, pi/M] and
+ * SID > 0, finite. */
+int ph_filter_response_equiangular(int M, double alpha, double sid, float *K);
 int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M,
                         const float *W_red, const float *W, int batch, int dtype, void *stream);
 
 /* ------------------------------------------------------- FBP / FDK
  * Eq. 4 (FBP) and Eq. 5 (FDK network): x = B F^H K F W_red W_cos p.
+ * Defaults: Ram-Lak K; W_cos the cosine weight SDD / sqrt(SDD^2 + u^2 + v^2)
+ * (cos(gamma_j) and the equiangular Ram-Lak response on the equiangular fan
+ * detector); W_red 1/2 for a full turn of a fan or cone scan, Parker for a
+ * short scan (at the bins' fan angles), pi/range for parallel beams.
  * Workspace: ws of ws_bytes >= ph_workspace_bytes_*() device bytes holds the
  * filtered projections. */
 size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch);

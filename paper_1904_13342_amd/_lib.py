@@ -27,6 +27,7 @@ class Geom2D(ctypes.Structure):
         ("sid", ctypes.c_float),
         ("sdd", ctypes.c_float),
         ("step_mm", ctypes.c_float),
+        ("fan_detector", ctypes.c_int),
     ]
 
 
@@ -89,6 +90,7 @@ SIGNATURES = {
     "ph_fbp_fan2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fdk_cone3d": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _P, _SZ, _I, _I, _P]),
     "ph_filter_response": (_I, [_I, _I, ctypes.c_double, _FP]),
+    "ph_filter_response_equiangular": (_I, [_I, ctypes.c_double, ctypes.c_double, _FP]),
     "ph_tv_3d": (_I, [_P, _I, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "ph_tv_workspace_bytes_2d": (_SZ, [_G2, _I]),
     "ph_tv_workspace_bytes_3d": (_SZ, [_G3, _I]),

@@ -103,6 +103,10 @@ int make_geom2d(const ph_geom2d *g, bool fan, Geom2D *o)
         return PH_ERR_GEOMETRY;
     if (fan && !(finite_pos(g->sid) && std::isfinite(g->sdd) && g->sdd > g->sid))
         return PH_ERR_GEOMETRY;
+    // equiangular detector: an arc of less than a half turn about the source
+    if (fan && g->fan_detector != 0 &&
+        (g->fan_detector != 1 || !((double)g->det_shape * g->det_spacing / g->sdd < kPi)))
+        return PH_ERR_GEOMETRY;
     o->ny = g->vol_shape[0];
     o->nx = g->vol_shape[1];
     o->sy = g->vol_spacing[0];
@@ -117,6 +121,7 @@ int make_geom2d(const ph_geom2d *g, bool fan, Geom2D *o)
     o->n_proj = g->n_proj;
     o->sid = fan ? g->sid : 0.0f;
     o->sdd = fan ? g->sdd : 0.0f;
+    o->curved = fan && g->fan_detector == 1 ? 1 : 0;
     o->step = (float)default_step(g->step_mm, std::fmin(g->vol_spacing[0], g->vol_spacing[1]));
     o->dbeta = (float)((double)g->angular_range / g->n_proj);
     return PH_OK;
@@ -373,6 +378,50 @@ const float *ramlak_table(int M, double tau, int *st)
     return (const float *)cached(key, [&] { return as_bytes(ramlak_response(M, tau)); }, st);
 }
 
+// Equiangular Ram-Lak (curved fan detector, Kak & Slaney's equiangular rays):
+// the ramp kernel of the fan angle gamma = n alpha times (gamma / sin gamma)^2,
+// with the SID of the equiangular pre-weight and the quadrature step alpha
+// folded into the taps, wrapped M-periodically and transformed like the
+// Ram-Lak response.
+double equiangular_tap(long n, double alpha, double sid)
+{
+    if (n == 0)
+        return 0.25 / (alpha * sid);
+    if (n % 2 == 0)
+        return 0.0;
+    const double sn = std::sin((double)n * alpha);
+    return -alpha / (kPi * kPi * sid * sn * sn);
+}
+
+// Taps with |n| > nmax are left out (n alpha stays below pi, where sin has no
+// zero); a row of nu bins filtered by linear convolution only meets lags
+// |n| <= nu - 1, so the default table stops there.
+std::vector<float> equiangular_response(int M, double alpha, double sid, long nmax)
+{
+    std::vector<float> K((size_t)M);
+    for (int k = 0; k < M; ++k) {
+        double acc = equiangular_tap(0, alpha, sid);
+        for (int n = 1; n < M; ++n) {
+            const long nn = n <= M / 2 ? n : n - M;
+            if (nn > nmax || -nn > nmax)
+                continue;
+            acc += equiangular_tap(nn, alpha, sid) * std::cos(2.0 * kPi * (double)(((long)k * n) % M) / M);
+        }
+        K[(size_t)k] = (float)acc;
+    }
+    return K;
+}
+
+const float *equiangular_table(int M, double alpha, double sid, int nu, int *st)
+{
+    std::string key = "eqang";
+    append(key, &M, 1);
+    append(key, &alpha, 1);
+    append(key, &sid, 1);
+    append(key, &nu, 1);
+    return (const float *)cached(key, [&] { return as_bytes(equiangular_response(M, alpha, sid, nu - 1)); }, st);
+}
+
 const float2 *twiddle_table(int M, int *st)
 {
     std::string key = "twiddle";
@@ -429,6 +478,8 @@ const float *wred_table(int kind, int n_proj, int nu, double du, double range, d
                         v = kPi / range;
                     else if (full)
                         v = 0.5;
+                    else if (kind == 3)   // equiangular bins: the fan angle is linear in j
+                        v = parker(beta, (j - 0.5 * (nu - 1)) * du / sdd, delta);
                     else
                         v = parker(beta, std::atan((j - 0.5 * (nu - 1)) * du / sdd), delta);
                     w[(size_t)k * nu + j] = (float)v;
@@ -531,6 +582,10 @@ int filter_len(const float *K, int M, int nu, int *Mout)
     return PH_OK;
 }
 
+// Filter kind of a 2D call: 0 parallel, 1 fan on the flat detector, 3 fan on
+// the equiangular detector (2 is the cone beam).
+int kind2d(const ph_geom2d *g, bool fan) { return !fan ? 0 : g->fan_detector == 1 ? 3 : 1; }
+
 // Filter arguments of a validated call (M from filter_len); uploads the
 // default tables on first use.
 int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, double dv, double sid, double sdd,
@@ -549,7 +604,8 @@ int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, doub
     a->cu = 0.5f * (float)(nu - 1);
     a->cv = 0.5f * (float)(nv - 1);
     a->cos_sdd = kind == 0 ? 0.0f : (float)sdd;
-    a->K = K ? K : ramlak_table(M, tau, &st);
+    a->curved = kind == 3 ? 1 : 0;
+    a->K = K ? K : kind == 3 ? equiangular_table(M, du / sdd, sid, nu, &st) : ramlak_table(M, tau, &st);
     if (st != PH_OK)
         return st;
     a->tw = twiddle_table(M, &st);
@@ -618,7 +674,7 @@ int weight_filter2d(const ph_geom2d *g, bool fan, const void *sino, float *out, 
     if (st != PH_OK)
         return st;
     FilterArgs a;
-    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+    st = filter_args(kind2d(g, fan), g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
                      g->angular_range, K, M, W_red, nullptr, &a);
     if (st != PH_OK)
         return st;
@@ -657,7 +713,7 @@ int fbp2d(const ph_geom2d *g, bool fan, const float *rv, const void *sino, void 
     if (st != PH_OK)
         return st;
     FilterArgs a;
-    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+    st = filter_args(kind2d(g, fan), g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
                      g->angular_range, K, M, W_red, nullptr, &a);
     if (st != PH_OK)
         return st;
@@ -1055,6 +1111,19 @@ int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, cons
     return bpT3d(g, mats, vol, proj, ws, ws_bytes, true, batch, dtype, stream);
 }
 
+int ph_filter_response_equiangular(int M, double alpha, double sid, float *K)
+{
+    if (!K)
+        return PH_ERR_NULL;
+    if (!is_pow2(M) || M < 2 || M > 4096)
+        return PH_ERR_SHAPE;
+    if (!finite_pos(alpha) || !(alpha * M <= kPi) || !finite_pos(sid))
+        return PH_ERR_VALUE;
+    const std::vector<float> t = equiangular_response(M, alpha, sid, M / 2);
+    std::copy(t.begin(), t.end(), K);
+    return PH_OK;
+}
+
 int ph_filter_response(int kind, int M, double tau, float *K)
 {
     if (!K)
@@ -1119,7 +1188,7 @@ int ph_corrector_grad_2d(const ph_geom2d *g, int fan, const float *sino, const f
     if (st != PH_OK)
         return st;
     FilterArgs a;
-    st = filter_args(fan ? 1 : 0, g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
+    st = filter_args(kind2d(g, fan), g->det_shape, 1, g->n_proj, batch, g->det_spacing, 1.0, g->sid, g->sdd,
                      g->angular_range, K, M, W_red, nullptr, &a);
     if (st != PH_OK)
         return st;

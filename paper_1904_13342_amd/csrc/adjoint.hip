@@ -50,7 +50,9 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
         for (int q = 0; q < 4; ++q) {
             const float x = (q & 1) ? x1 : x0, y = (q & 2) ? y1 : y0;
             const float xu = -x * c.y + y * c.x;
-            const float su = FAN ? g.sdd * xu / fmaf(x, c.x, fmaf(y, c.y, g.sid)) : xu;
+            const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
+            // detector coordinate in mm (arc length on the equiangular detector)
+            const float su = !FAN ? xu : g.curved ? g.sdd * atan2f(xu, w) : g.sdd * xu / w;
             smin = fminf(smin, su);
             smax = fmaxf(smax, su);
         }
@@ -239,21 +241,17 @@ __global__ void __launch_bounds__(256) bpT2d_kernel(Geom2D g, const float2 *__re
     const float rdu = 1.0f / g.du;
     for (int k = 0; k < g.n_proj; ++k) {
         const float2 c = views[k];
-        const float xu = -x * c.y + y * c.x;
-        float su, wt;
+        int j;
+        float t, wt;
         if (!FAN) {
-            su = fmaf(xu, rdu, g.cu);
+            const float su = fmaf(-x * c.y + y * c.x, rdu, g.cu);
+            const float fu = floorf(su);
+            j = (int)fu;
+            t = su - fu;
             wt = 1.0f;
         } else {
-            const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
-            const float rw = 1.0f / w;
-            su = fmaf(g.sdd * xu * rw, rdu, g.cu);
-            const float sw = g.sid * rw;
-            wt = sw * sw;
+            fan2d_point(g, c, ix, iy, j, t, wt);
         }
-        const float fu = floorf(su);
-        const int j = (int)fu;
-        const float t = su - fu;
         const float v = g.dbeta * wt * val;
         if (j >= 0 && j < g.nu)
             unsafeAtomicAdd(sb + (size_t)k * g.nu + j, v * (1.0f - t));

@@ -37,6 +37,7 @@ __device__ __forceinline__ void store_f32(bf16_t *p, float v)
 
 struct Geom2D {
     int nx, ny, nu, n_proj;
+    int curved;            // fan beams: 1 for the equiangular (arc) detector, 0 for the flat one
     float ox, oy;          // world mm of pixel (0,0)
     float inv_sx, inv_sy;  // 1 / spacing
     float sx, sy;
@@ -116,13 +117,28 @@ hipError_t fill_zero(float *p, size_t n, hipStream_t stream);
 struct FilterArgs {
     int nu, nv, n_proj, batch, M, log2M;
     float du, dv, cu, cv;
-    float cos_sdd;       // > 0: apply SDD / sqrt(SDD^2 + u^2 + v^2)
+    float cos_sdd;       // > 0: apply SDD / sqrt(SDD^2 + u^2 + v^2), or cos(u / SDD) if curved
+    int curved;          // 2D fan beam on the equiangular (arc) detector
     const float *K;      // device [M]
     const float2 *tw;    // device [M] exp(-2 pi i t / M)
     const float *W_red;  // device [n_proj][nu] or NULL
     const float *W;      // device [nv][nu] or NULL
 };
 hipError_t launch_weight_filter(int dtype, const FilterArgs &a, const void *in, float *out, hipStream_t stream);
+
+// Cosine weight of detector pixel (i, j) (Kak & Slaney): SDD / sqrt(SDD^2 +
+// u^2 + v^2) on a flat detector, cos(gamma_j) with gamma_j = u / SDD on the
+// equiangular arc, 1 for parallel beams (cos_sdd = 0).
+__device__ __forceinline__ float cosine_weight(const FilterArgs &a, int i, int j)
+{
+    if (a.cos_sdd <= 0.0f)
+        return 1.0f;
+    const float u = ((float)j - a.cu) * a.du;
+    if (a.curved)
+        return cosf(u / a.cos_sdd);
+    const float v = ((float)i - a.cv) * a.dv;
+    return a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
+}
 
 // Learned-corrector training (FP32)
 hipError_t launch_mse(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss,

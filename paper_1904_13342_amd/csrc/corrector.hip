@@ -57,11 +57,7 @@ __global__ void __launch_bounds__(256) mse_kernel(const float *__restrict__ x, c
 // view k (no cosine weight for parallel beams, cos_sdd = 0)
 __device__ __forceinline__ float pixel_weight(const FilterArgs &a, int k, int i, int j)
 {
-    const float wr = a.W_red[(size_t)k * a.nu + j];
-    if (a.cos_sdd <= 0.0f)
-        return wr;
-    const float u = ((float)j - a.cu) * a.du, v = ((float)i - a.cv) * a.dv;
-    return wr * a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
+    return a.W_red[(size_t)k * a.nu + j] * cosine_weight(a, i, j);
 }
 
 template <int M>

@@ -58,7 +58,9 @@ __device__ __forceinline__ float ray_coord_biased(float p_biased, float e, int m
 
 // Ray of 2D detector bin j in a view with central ray vector c: index
 // coordinates (x, y) of its anchor and of one step (fan rays set up in double
-// precision for the same reason as cone rays).
+// precision for the same reason as cone rays).  On the equiangular detector
+// bin j sits at fan angle u / SDD on the arc of radius SDD about the source,
+// so its ray is the central ray turned by that angle.
 template <bool FAN>
 __device__ __forceinline__ void make_ray_2d(const Geom2D &g, float2 c, int j, float &X0, float &Y0, float &eX,
                                             float &eY)
@@ -71,6 +73,14 @@ __device__ __forceinline__ void make_ray_2d(const Geom2D &g, float2 c, int j, fl
         ay = u * ey;
         dx = cx;
         dy = cy;
+    } else if (g.curved) {
+        const double gam = u / (double)g.sdd, cg = cos(gam), sg = sin(gam);
+        const double sx = -(double)g.sid * cx, sy = -(double)g.sid * cy;
+        dx = cg * cx + sg * ex;
+        dy = cg * cy + sg * ey;
+        const double t0 = -(sx * dx + sy * dy);
+        ax = fma(t0, dx, sx);
+        ay = fma(t0, dy, sy);
     } else {
         const double sx = -(double)g.sid * cx, sy = -(double)g.sid * cy;
         const double tx = (double)g.sdd * cx + u * ex, ty = (double)g.sdd * cy + u * ey;  // detector - source
@@ -85,6 +95,40 @@ __device__ __forceinline__ void make_ray_2d(const Geom2D &g, float2 c, int j, fl
     Y0 = (float)((ay - (double)g.oy) / (double)g.sy);
     eX = (float)((double)g.step * dx / (double)g.sx);
     eY = (float)((double)g.step * dy / (double)g.sy);
+}
+
+// Detector bin j, fraction t in [0, 1) and distance weight of pixel (ix, iy)
+// in a fan view with central ray c: central projection onto the flat detector
+// with weight (SID / w)^2, w the depth along the central ray; on the
+// equiangular detector the bin of the pixel's fan angle, with weight
+// (SID / L)^2, L the distance from the source.  For the equiangular detector
+// the pixel position, its fan angle, bin and fraction are formed in double
+// precision (in FP32 the position and the arctangent alone misplace wide-fan
+// samples by a few 1e-6 bin).  The back-projector and its transpose both use
+// this, so they see the same coordinates.
+__device__ __forceinline__ void fan2d_point(const Geom2D &g, float2 c, int ix, int iy, int &j, float &t, float &wt)
+{
+    if (g.curved) {
+        const double x = fma((double)ix, (double)g.sx, (double)g.ox), y = fma((double)iy, (double)g.sy, (double)g.oy);
+        const double xu = fma(y, (double)c.x, -x * (double)c.y);
+        const double w = fma(x, (double)c.x, fma(y, (double)c.y, (double)g.sid));
+        const double s = fma(atan2(xu, w), (double)g.sdd / (double)g.du, (double)g.cu);
+        const double fs = floor(s);
+        j = (int)fs;
+        t = (float)(s - fs);
+        wt = (float)((double)g.sid * (double)g.sid / fma(w, w, xu * xu));
+    } else {
+        const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
+        const float xu = -x * c.y + y * c.x;
+        const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
+        const float rw = 1.0f / w;
+        const float su = fmaf(g.sdd * xu * rw, 1.0f / g.du, g.cu);
+        const float fu = floorf(su);
+        j = (int)fu;
+        t = su - fu;
+        const float sw = g.sid * rw;
+        wt = sw * sw;
+    }
 }
 
 // Narrow [lo, hi] to the parameters t with p + t e inside the open interval

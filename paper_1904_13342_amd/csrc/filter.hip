@@ -27,10 +27,7 @@ __device__ __forceinline__ float weighted(const FilterArgs &a, const T *in, long
         w *= a.W_red[(size_t)k * a.nu + j];
     if (a.W)
         w *= a.W[(size_t)i * a.nu + j];
-    if (a.cos_sdd > 0.0f) {
-        const float u = ((float)j - a.cu) * a.du, v = ((float)i - a.cv) * a.dv;
-        w *= a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
-    }
+    w *= cosine_weight(a, i, j);
     return w * load_f32(in + (size_t)row * a.nu + j);
 }
 

@@ -82,21 +82,17 @@ __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__res
     float acc = 0.0f;
     for (int k = 0; k < g.n_proj; ++k) {
         const float2 c = views[k];
-        const float xu = -x * c.y + y * c.x;
-        float su, wt;
+        int j;
+        float t, wt;
         if (!FAN) {
-            su = fmaf(xu, rdu, g.cu);
+            const float su = fmaf(-x * c.y + y * c.x, rdu, g.cu);
+            const float fu = floorf(su);
+            j = (int)fu;
+            t = su - fu;
             wt = 1.0f;
         } else {
-            const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
-            const float rw = 1.0f / w;
-            su = fmaf(g.sdd * xu * rw, rdu, g.cu);
-            const float sw = g.sid * rw;
-            wt = sw * sw;
+            fan2d_point(g, c, ix, iy, j, t, wt);
         }
-        const float fu = floorf(su);
-        const int j = (int)fu;
-        const float t = su - fu;
         const TI *row = sb + (size_t)k * g.nu;
         const float p0 = (j >= 0 && j < g.nu) ? load_f32(row + j) : 0.0f;
         const float p1 = (j + 1 >= 0 && j + 1 < g.nu) ? load_f32(row + j + 1) : 0.0f;

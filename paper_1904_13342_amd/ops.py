@@ -22,9 +22,13 @@ _DTYPES = {torch.float32: PH_F32, torch.float16: PH_F16, torch.bfloat16: PH_BF16
 # ------------------------------------------------------------------ geometry
 
 def geom2d(vol_shape, vol_spacing, det_shape, det_spacing, n_proj, angular_range, sid=0.0, sdd=0.0, step_mm=0.0,
-           vol_origin=None):
+           vol_origin=None, detector="flat"):
     """ph_geom2d record; shapes/spacings in (y, x) order; origin defaults to a
-    grid centred on the rotation axis."""
+    grid centred on the rotation axis.  ``detector`` (fan beams): "flat" or
+    "curved" (equiangular arc of radius SDD about the source, det_spacing the
+    arc length between bins)."""
+    if detector not in ("flat", "curved"):
+        raise ValueError('detector must be "flat" or "curved"')
     g = Geom2D()
     vol_shape = tuple(int(v) for v in vol_shape)
     vol_spacing = tuple(float(v) for v in vol_spacing)
@@ -38,6 +42,7 @@ def geom2d(vol_shape, vol_spacing, det_shape, det_spacing, n_proj, angular_range
     g.n_proj = int(n_proj)
     g.angular_range = float(angular_range)
     g.sid, g.sdd, g.step_mm = float(sid), float(sdd), float(step_mm)
+    g.fan_detector = 1 if detector == "curved" else 0
     return g
 
 
@@ -63,13 +68,15 @@ def geom3d(vol_shape, vol_spacing, det_shape, det_spacing, n_proj, angular_range
 def from_spec(spec):
     """Geometry record from any object with the attributes kind, vol_shape,
     vol_spacing, det_shape, det_spacing, n_proj, angular_range, sid, sdd,
-    step_mm (and optionally vol_origin)."""
+    step_mm (and optionally vol_origin); kind "fan2d_curved" selects the
+    equiangular fan detector (use the *_fan2d calls with it)."""
     origin = getattr(spec, "vol_origin", None)
     if spec.kind == "cone3d":
         return geom3d(spec.vol_shape, spec.vol_spacing, spec.det_shape, spec.det_spacing, spec.n_proj,
                       spec.angular_range, spec.sid, spec.sdd, spec.step_mm, origin)
     return geom2d(spec.vol_shape, spec.vol_spacing, spec.det_shape, spec.det_spacing, spec.n_proj,
-                  spec.angular_range, spec.sid, spec.sdd, spec.step_mm, origin)
+                  spec.angular_range, spec.sid, spec.sdd, spec.step_mm, origin,
+                  detector="curved" if spec.kind == "fan2d_curved" else "flat")
 
 
 def _fptr(a):
@@ -273,6 +280,15 @@ def filter_response(kind, M, tau):
         raise ValueError(f"kind must be one of {sorted(kinds)}")
     K = (ctypes.c_float * int(M))()
     check("ph_filter_response", lib().ph_filter_response(kinds[kind], int(M), float(tau), K))
+    return torch.tensor(list(K), dtype=torch.float32)
+
+
+def filter_response_equiangular(M, alpha, sid):
+    """Host float32 [M] equiangular Ram-Lak response (curved fan detector,
+    angular bin pitch alpha = du / SDD)."""
+    K = (ctypes.c_float * int(M))()
+    check("ph_filter_response_equiangular",
+          lib().ph_filter_response_equiangular(int(M), float(alpha), float(sid), K))
     return torch.tensor(list(K), dtype=torch.float32)
 
 
@@ -489,6 +505,7 @@ __all__ = [
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "filter_response", "tv", "tv_workspace_bytes", "tv_iterate", "mse_grad",
+    "fbp_fan2d", "fdk_cone3d", "filter_response", "filter_response_equiangular", "tv", "tv_workspace_bytes",
+    "tv_iterate", "mse_grad",
     "corrector_grad_3d", "corrector_grad_2d", "adam_step", "version",
 ]

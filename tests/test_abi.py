@@ -251,6 +251,36 @@ def test_filter_response_matches_oracle(L, ora):
     assert L.ph_filter_response(1, 16, -1.0, K) == -8
 
 
+def test_equiangular_response_matches_oracle(L, ora):
+    for M, alpha, sid in ((16, 0.05, 300.0), (2048, 1.0 / 1200.0, 750.0)):
+        K = (ctypes.c_float * M)()
+        assert L.ph_filter_response_equiangular(M, alpha, sid, K) == 0
+        ref = ora.equiangular_response(M, alpha, sid)
+        assert np.abs(np.array(K) - ref).max() <= 1e-6 * np.abs(ref).max()
+    K = (ctypes.c_float * 16)()
+    assert L.ph_filter_response_equiangular(16, 0.05, 300.0, None) == -1
+    assert L.ph_filter_response_equiangular(24, 0.05, 300.0, K) == -2
+    assert L.ph_filter_response_equiangular(16, 0.5, 300.0, K) == -8   # alpha * M > pi
+    assert L.ph_filter_response_equiangular(16, 0.05, -1.0, K) == -8
+
+
+def test_curved_fan_detector_validation(ph, L):
+    """fan_detector must be 0 or 1, and the arc must span less than a half
+    turn about the source."""
+    spec = synth.config("fan2d_512").with_(kind="fan2d_curved")
+    g = ph.from_spec(spec)
+    assert g.fan_detector == 1
+    rv = ph.ray_vectors_2d(g)
+    fp = rv.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    g.fan_detector = 2
+    assert L.ph_project_fan2d(ctypes.byref(g), fp, FAKE, FAKE, 1, 0, None) == -3
+    g.fan_detector = 1
+    g.det_spacing = 6.0    # 725 bins * 6 mm / 1200 mm > pi rad
+    assert L.ph_project_fan2d(ctypes.byref(g), fp, FAKE, FAKE, 1, 0, None) == -3
+    with pytest.raises(ValueError):
+        ph.geom2d((8, 8), (1.0, 1.0), 12, 1.0, 4, math.pi, 20.0, 32.0, detector="round")
+
+
 def test_binding_checks_tensor_shapes(ph):
     import torch
     g = ph.from_spec(synth.config("par2d_64"))
