@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--config", default="cone3d_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("fdk", "corrector", "tv", "filter2d", "precision", "copyref"),
+    ap.add_argument("--workload", choices=("fdk", "corrector", "tv", "filter2d", "fan2d", "precision", "copyref"),
                     default="fdk",
                     help="fdk: the projector / FDK hot path (default); corrector: the learned-corrector training run; "
                          "tv: sparse-view TV-regularised iterative reconstruction; "
@@ -342,6 +342,93 @@ def tv_main(args):
     print(json.dumps(line), flush=True)
 
 
+def count_samples_2d(spec, curved, device):
+    """Ray samples of a 2D fan geometry inside the open index box (-1, N)^2,
+    counted in float64 like count_samples (flat or equiangular detector)."""
+    import torch
+    ny, nx = spec.vol_shape
+    sy, sx = spec.vol_spacing
+    oy, ox = spec.origin
+    nu, du = spec.det_shape[0], spec.det_spacing[0]
+    u = (torch.arange(nu, dtype=torch.float64, device=device) - (nu - 1) / 2) * du
+    total = 0
+    for k in range(spec.n_proj):
+        b = spec.angular_range * k / spec.n_proj
+        c, e = (math.cos(b), math.sin(b)), (-math.sin(b), math.cos(b))
+        src = (-spec.sid * c[0], -spec.sid * c[1])
+        if curved:
+            gam = u / spec.sdd
+            dx, dy = torch.cos(gam) * c[0] + torch.sin(gam) * e[0], torch.cos(gam) * c[1] + torch.sin(gam) * e[1]
+        else:
+            dx, dy = spec.sdd * c[0] + u * e[0], spec.sdd * c[1] + u * e[1]
+            n = torch.sqrt(dx * dx + dy * dy)
+            dx, dy = dx / n, dy / n
+        t0 = -(src[0] * dx + src[1] * dy)
+        lo = torch.full_like(u, -math.inf)
+        hi = torch.full_like(u, math.inf)
+        for a, d, o, sp, N in ((src[0], dx, ox, sx, nx), (src[1], dy, oy, sy, ny)):
+            p0 = (a + t0 * d - o) / sp
+            ed = spec.step * d / sp
+            t1, t2 = (-1.0 - p0) / ed, (N - p0) / ed
+            lo = torch.maximum(lo, torch.minimum(t1, t2))
+            hi = torch.minimum(hi, torch.maximum(t1, t2))
+        n_in = torch.clamp(torch.ceil(hi) - torch.floor(lo) - 1, min=0)
+        total += int(n_in.sum().item())
+    return total
+
+
+def fan2d_main(args):
+    """The 2D fan-beam workload (512^2 at 0.5 mm of 10 seeded random ellipses,
+    360 views over 360 deg, 725 bins of 1 mm, SID 750 mm, SDD 1200 mm) on the
+    flat and on the equiangular (curved) detector: forward projection and
+    FBP (weighting, filter, back-projection) timed with HIP events (median of
+    five), and the FBP's RMSE against the phantom."""
+    import torch
+
+    import paper_1904_13342_amd as ph
+    import synth
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, kind in (("flat", "fan2d"), ("curved", "fan2d_curved")):
+        spec = synth.config("fan2d_512").with_(kind=kind)
+        g = ph.from_spec(spec)
+        rv = ph.ray_vectors_2d(g)
+        prm = synth.random_ellipses(spec.seed, spec.n_figures, spec.vol_shape, spec.vol_spacing)
+        f = synth.rasterize_ellipses(prm, spec.vol_shape, spec.vol_spacing, sub=4).to(dev, torch.float32).contiguous()
+        p = torch.empty((spec.n_proj, spec.det_shape[0]), dtype=torch.float32, device=dev)
+        x = torch.empty_like(f)
+        ws = torch.empty(ph.workspace_bytes_2d(g, 1), dtype=torch.uint8, device=dev)
+        ph.fbp_fan2d(g, rv, ph.project_fan2d(g, rv, f, out=p), out=x, ws=ws)   # warm-up
+        torch.cuda.synchronize()
+        fp_ms, fbp_ms = [], []
+        for _ in range(5):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            ph.project_fan2d(g, rv, f, out=p)
+            ev[1].record()
+            ph.fbp_fan2d(g, rv, p, out=x, ws=ws)
+            ev[2].record()
+            torch.cuda.synchronize()
+            fp_ms.append(ev[0].elapsed_time(ev[1]))
+            fbp_ms.append(ev[1].elapsed_time(ev[2]))
+        fp_t, fbp_t = sorted(fp_ms)[2], sorted(fbp_ms)[2]
+        samples = count_samples_2d(spec, name == "curved", dev)
+        updates = spec.vol_shape[0] * spec.vol_shape[1] * spec.n_proj
+        out[name] = {"fp_ms": fp_t, "fbp_ms": fbp_t, "fp_gsamples_per_s": samples / fp_t / 1e6,
+                     "fbp_gups": updates / fbp_t / 1e6, "samples": samples,
+                     "rmse_fbp": float(((x.double() - f.double()) ** 2).mean().sqrt())}
+    line = {
+        "metric": "2D fan-beam forward projection Gsamples/s and FBP GUPS, flat vs equiangular detector",
+        "value": out["curved"]["fbp_gups"], "unit": "GUPS (FBP, curved detector)", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic: 10 seeded random ellipses",
+        "config": {"workload": "fan2d 512x512 at 0.5 mm, 360 views over 360 deg, 725 bins at 1 mm "
+                               "(flat pitch or arc length), SID 750, SDD 1200"},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def filter2d_main(args):
     """Learning the reconstruction filter alone (Sec. III.B, Eq. 6): 2D
     parallel beam, 256^2 at 1 mm, 360 views over 180 deg, 363 bins at 1 mm,
@@ -473,6 +560,9 @@ def main():
         return
     if args.workload == "precision":
         precision_main(args)
+        return
+    if args.workload == "fan2d":
+        fan2d_main(args)
         return
     if args.workload == "copyref":
         import torch
