@@ -185,13 +185,17 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
                 }
                 if (gv == 0.0f)
                     continue;
+                // the samples that can reach the support: the clip only picks
+                // the range to visit (hardware reciprocals, widened by a step
+                // on each side); the exact test below decides every sample
                 float lo = -3.0e38f, hi = 3.0e38f;
-                if (!clip_line(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) || !clip_line(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) ||
-                    !clip_line(Z0, eZ, zlo, zhi, lo, hi) || !(lo < hi))
+                if (!clip_line_rcp(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) ||
+                    !clip_line_rcp(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) || !clip_line_rcp(Z0, eZ, zlo, zhi, lo, hi) ||
+                    !(lo < hi + 0.01f))   // reciprocal error is below 1e-3 step at these ranges
                     continue;
                 // the projector's biased sample positions, un-biased exactly
                 const float Xb = X0 + RAY_BIAS, Yb = Y0 + RAY_BIAS, Zb = Z0 + RAY_BIAS;
-                for (int m = (int)floorf(lo); m <= (int)ceilf(hi); ++m) {
+                for (int m = (int)floorf(lo) - 1; m <= (int)ceilf(hi) + 1; ++m) {
                     const float X = ray_coord_biased(Xb, eX, m) - RAY_BIAS;
                     const float Y = ray_coord_biased(Yb, eY, m) - RAY_BIAS;
                     const float Z = ray_coord_biased(Zb, eZ, m) - RAY_BIAS;

@@ -143,6 +143,20 @@ __device__ __forceinline__ bool clip_line(float p, float e, float a, float b, fl
     return true;
 }
 
+// clip_line with the hardware reciprocal in place of the divisions: the
+// bounds may be off by a few ulps, so callers widen the range they derive and
+// test each sample exactly.
+__device__ __forceinline__ bool clip_line_rcp(float p, float e, float a, float b, float &lo, float &hi)
+{
+    if (fabsf(e) < 1e-30f)
+        return p > a && p < b;
+    const float r = __builtin_amdgcn_rcpf(e);
+    const float t1 = (a - p) * r, t2 = (b - p) * r;
+    lo = fmaxf(lo, fminf(t1, t2));
+    hi = fminf(hi, fmaxf(t1, t2));
+    return true;
+}
+
 __device__ __forceinline__ float dot4(const float r[4], float x, float y, float z)
 {
     return fmaf(r[0], x, fmaf(r[1], y, fmaf(r[2], z, r[3])));
