@@ -241,12 +241,15 @@ def test_short_training_beats_ramp_initialisation(ph):
     assert r1 < r0 and r1 < plain
 
 
-@pytest.mark.parametrize("fan", [False, True])
-def test_corrector_grad_2d_parity(ph, ora, fan):
-    base = synth.config("fan2d_512") if fan else synth.config("par2d_64")
+@pytest.mark.parametrize("det", ["parallel", "flat", "curved"])
+def test_corrector_grad_2d_parity(ph, ora, det):
+    base = synth.config("par2d_64") if det == "parallel" else synth.config("fan2d_512")
     spec = base.with_(vol_shape=(33, 29), vol_spacing=(1.0, 1.1), det_shape=(47,), det_spacing=(1.3,), n_proj=23,
                       sid=60.0, sdd=100.0)
-    say(f"[corrector_grad_2d] fan={fan}")
+    if det == "curved":
+        spec = spec.with_(kind="fan2d_curved")
+    fan = det != "parallel"
+    say(f"[corrector_grad_2d] {det}")
     p = _rng_tensor((2, spec.n_proj, 47), 80, 1.0, 2.0)
     gq = _rng_tensor((2, spec.n_proj, 47), 81)
     K = to_dev(as_f32(ora.ramp_response(128, ora.tau(spec)) + 0.05 * synth.random_array((128,), 82)))

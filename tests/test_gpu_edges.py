@@ -1,6 +1,7 @@
 """Degenerate and extreme cases on the GPU, against the oracle: a one-voxel
 volume and one-pixel detector, a single view, a one-slice cone volume, views
-at exact multiples of 45 degrees (the dominant-axis tie), odd detector sizes
+at exact multiples of 45 degrees (the dominant-axis tie; flat and curved fan
+detectors), odd detector sizes
 (rays exactly along the grid axes through the centre row and column), and
 the longest filter (M = 4096)."""
 import math
@@ -33,7 +34,7 @@ def _all_ops(ph, ora, spec, seed):
         rec = lambda p: ph.fdk_cone3d(g, traj, p)
     else:
         traj = ph.ray_vectors_2d(g)
-        fan = spec.kind == "fan2d"
+        fan = spec.kind in ("fan2d", "fan2d_curved")
         A = ph.project_fan2d if fan else ph.project_par2d
         B = ph.backproject_fan2d if fan else ph.backproject_par2d
         AT = ph.project_adjoint_fan2d if fan else ph.project_adjoint_par2d
@@ -74,6 +75,12 @@ CASES = {
     "par2d_single_view_odd": synth.config("par2d_64").with_(vol_shape=(15, 17), det_shape=(25,), n_proj=1),
     "fan2d_octant_views": synth.config("fan2d_512").with_(vol_shape=(31, 33), vol_spacing=(1.0, 1.0),
                                                           det_shape=(61,), n_proj=8, sid=120.0, sdd=200.0),
+    "fan2d_curved_octant_views": synth.config("fan2d_512").with_(kind="fan2d_curved", vol_shape=(31, 33),
+                                                                 vol_spacing=(1.0, 1.0), det_shape=(61,), n_proj=8,
+                                                                 sid=120.0, sdd=200.0),
+    "fan2d_curved_one_pixel_one_bin": synth.config("fan2d_512").with_(kind="fan2d_curved", vol_shape=(1, 1),
+                                                                      vol_spacing=(1.0, 1.0), det_shape=(1,),
+                                                                      n_proj=3, sid=50.0, sdd=80.0),
 }
 
 

@@ -108,12 +108,15 @@ def test_iteration_parity(ph, ora):
     assert ex < 1e-5
 
 
-@pytest.mark.parametrize("kind", ["par2d", "fan2d", "cone3d"])
+@pytest.mark.parametrize("kind", ["par2d", "fan2d", "fan2d_curved", "cone3d"])
 def test_library_loop_matches_composed_steps(ph, ora, kind):
     """TVReconstruction.run (the loop inside the library) gives the iterates
-    of the composed per-call steps."""
-    spec = {"par2d": SPARSE, "fan2d": synth.config("fan2d_512").with_(vol_shape=(40, 36), n_proj=24, det_shape=(90,)),
+    of the composed per-call steps (the curved fan detector runs the fan
+    calls with an equiangular geometry)."""
+    fan = synth.config("fan2d_512").with_(vol_shape=(40, 36), n_proj=24, det_shape=(90,))
+    spec = {"par2d": SPARSE, "fan2d": fan, "fan2d_curved": fan.with_(kind="fan2d_curved"),
             "cone3d": synth.config("cone3d_crop32").with_(n_proj=20)}[kind]
+    kind = "fan2d" if kind == "fan2d_curved" else kind
     f = gc.phantom(spec)
     p = as_f32(ora.project(spec, f))
     g = ph.from_spec(spec)
