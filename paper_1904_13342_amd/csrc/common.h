@@ -134,10 +134,10 @@ __device__ __forceinline__ float cosine_weight(const FilterArgs &a, int i, int j
     if (a.cos_sdd <= 0.0f)
         return 1.0f;
     const float u = ((float)j - a.cu) * a.du;
-    if (a.curved)
-        return cosf(u / a.cos_sdd);
+    if (a.curved)   // |gamma| < pi / 2: the hardware cosine is accurate to a few ulp here
+        return __cosf(u * (1.0f / a.cos_sdd));
     const float v = ((float)i - a.cv) * a.dv;
-    return a.cos_sdd / sqrtf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
+    return a.cos_sdd * __builtin_amdgcn_rsqf(fmaf(a.cos_sdd, a.cos_sdd, fmaf(u, u, v * v)));
 }
 
 // Learned-corrector training (FP32)

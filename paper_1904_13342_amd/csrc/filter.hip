@@ -79,6 +79,244 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
     }
 }
 
+// ----------------------------------------------------------------- M = 2048
+// One wave per pair of rows (a + i b as above), no workgroup barriers after
+// set-up.  The 2048-point transform is taken as 32 x 64 (four-step):
+//   n = 64 a + b, k = c + 32 d:  X[c + 32 d] = sum_b w64^(b d) w2048^(b c) sum_a x[64 a + b] w32^(a c).
+// Lane b holds x[64 a + b] (a = 0..31) and takes the 32-point DFT over a in
+// registers, multiplies by w2048^(b c) and writes row c of a wave-private LDS
+// transpose; lane (c, p) then reads the even (p = 0) or odd (p = 1) b of
+// row c, takes the 32-point DFT over them and one xor-1 exchange forms
+// X[c + 32 (d' + 32 p)].  After the multiply by K the inverse runs the same
+// steps backwards, and lane b ends with y[64 a + b], of which n < nu is kept.
+namespace w2k {
+
+constexpr int WAVES = 4;
+constexpr int TS = 65;          // forward transpose [c][b], row stride (float2): conflict-free b64 accesses
+constexpr int US = 33;          // inverse transpose [b][c], row stride (float2)
+constexpr int BUF = 64 * US;    // float2 per wave (>= 32 * TS)
+constexpr int KS = 1028;        // symmetrised response k = 0..1024 (floats, padded)
+
+__device__ constexpr int rev5(int k)
+{
+    return ((k & 1) << 4) | ((k & 2) << 2) | (k & 4) | ((k & 8) >> 2) | ((k & 16) >> 4);
+}
+
+// d * exp(DIR * 2 pi i t / 32) for t resolved at compile time after unrolling
+template <int DIR>
+__device__ __forceinline__ float2 tw32(float2 d, int t)
+{
+    constexpr float C[16] = {1.000000000e+00f, 9.807852507e-01f, 9.238795042e-01f, 8.314695954e-01f,
+                             7.071067691e-01f, 5.555702448e-01f, 3.826834261e-01f, 1.950903237e-01f,
+                             0.0f,             -1.950903237e-01f, -3.826834261e-01f, -5.555702448e-01f,
+                             -7.071067691e-01f, -8.314695954e-01f, -9.238795042e-01f, -9.807852507e-01f};
+    constexpr float S[16] = {0.000000000e+00f, 1.950903237e-01f, 3.826834261e-01f, 5.555702448e-01f,
+                             7.071067691e-01f, 8.314695954e-01f, 9.238795042e-01f, 9.807852507e-01f,
+                             1.000000000e+00f, 9.807852507e-01f, 9.238795042e-01f, 8.314695954e-01f,
+                             7.071067691e-01f, 5.555702448e-01f, 3.826834261e-01f, 1.950903237e-01f};
+    if (t == 0)
+        return d;
+    if (t == 8)   // exp(DIR i pi/2) = DIR * i
+        return DIR < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+    return cmul(d, make_float2(C[t], DIR * S[t]));
+}
+
+// In-register 32-point DFT (radix-2 decimation in frequency): natural order
+// in, bit-reversed order out (X[k] = v[rev5(k)]).
+template <int DIR>
+__device__ __forceinline__ void dft32(float2 (&v)[32])
+{
+#pragma unroll
+    for (int s = 16; s >= 1; s >>= 1) {
+#pragma unroll
+        for (int j = 0; j < 32; j += 2 * s) {
+#pragma unroll
+            for (int k = 0; k < s; ++k) {
+                const float2 x = v[j + k], y = v[j + k + s];
+                v[j + k] = cadd(x, y);
+                v[j + k + s] = tw32<DIR>(csub(x, y), k * (16 / s));
+            }
+        }
+    }
+}
+
+// the value of lane (lane xor 1): DPP quad permutation [1, 0, 3, 2]
+__device__ __forceinline__ float xor1f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 xor1(float2 x) { return make_float2(xor1f(x.x), xor1f(x.y)); }
+
+// One detector row as a buffer resource: loads past its end (or from an
+// absent row, bytes = 0) return 0 without a branch.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ float row_load(__amdgpu_buffer_rsrc_t r, int j);
+template <> __device__ __forceinline__ float row_load<float>(__amdgpu_buffer_rsrc_t r, int j)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, j * 4, 0, 0));
+}
+template <> __device__ __forceinline__ float row_load<f16_t>(__amdgpu_buffer_rsrc_t r, int j)
+{
+    return (float)__builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, j * 2, 0, 0));
+}
+template <> __device__ __forceinline__ float row_load<bf16_t>(__amdgpu_buffer_rsrc_t r, int j)
+{
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, j * 2, 0, 0) << 16);
+}
+
+// exp(-2 pi i t / 2048) for t in [0, 2048) from the half table
+__device__ __forceinline__ float2 w2048(const float2 *tw, int t)
+{
+    const float2 w = tw[t & 1023];
+    return t & 1024 ? make_float2(-w.x, -w.y) : w;
+}
+
+// orders the wave's LDS writes before its lanes read each other's values
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace w2k
+
+template <typename T>
+__global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) weight_filter_2048_kernel(FilterArgs a, const T *__restrict__ in,
+                                                                             float *__restrict__ out, long rows)
+{
+    using namespace w2k;
+    __shared__ float2 lds[1024 + KS / 2 + WAVES * BUF];
+    float2 *tw = lds;                                   // [1024]
+    float *ks = (float *)(lds + 1024);                  // [KS]
+    float2 *buf = lds + 1024 + KS / 2 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
+    for (int n = threadIdx.x; n < 1024; n += WAVES * 64)
+        tw[n] = a.tw[n];
+    for (int n = threadIdx.x; n <= 1024; n += WAVES * 64)
+        ks[n] = 0.5f * (a.K[n] + a.K[(2048 - n) & 2047]);
+    __syncthreads();
+    const float inv = 1.0f / 2048.0f;
+    const long pairs = (rows + 1) / 2;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
+    for (long pr = (long)blockIdx.x * WAVES + wave; pr < pairs; pr += (long)gridDim.x * WAVES) {
+        const long ra = 2 * pr, rb = ra + 1;
+        const bool has_b = rb < rows;
+        // The lane index is made opaque per pair so that per-column terms
+        // are recomputed rather than hoisted out of the loop and spilled.
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));
+        const int c = lane >> 1, p = lane & 1;          // roles in the middle steps
+        // the pair's rows packed as one complex sequence, lane b holding
+        // x[64 a + b]: all loads in flight at once, zero past nu
+        const unsigned row_bytes = (unsigned)a.nu * (unsigned)sizeof(T);
+        const __amdgpu_buffer_rsrc_t sa = row_rsrc(in + (size_t)ra * a.nu, row_bytes);
+        const __amdgpu_buffer_rsrc_t sb = row_rsrc(in + (size_t)rb * a.nu * has_b, has_b ? row_bytes : 0u);
+        float2 v[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            v[i] = make_float2(row_load<T>(sa, 64 * i + lane), row_load<T>(sb, 64 * i + lane));
+        // the weights, one wave-uniform pass per factor present
+        const int ia = (int)(ra % a.nv), ka = (int)((ra / a.nv) % a.n_proj);
+        const int ib = (int)(rb % a.nv), kb = (int)((rb / a.nv) % a.n_proj);
+        if (a.cos_sdd > 0.0f && a.curved) {   // cos(gamma_j), the same for both rows
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const float w = cosine_weight(a, ia, 64 * i + lane);
+                v[i].x *= w;
+                v[i].y *= w;
+            }
+        } else if (a.cos_sdd > 0.0f) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                v[i].x *= cosine_weight(a, ia, 64 * i + lane);
+                v[i].y *= cosine_weight(a, ib, 64 * i + lane);
+            }
+        }
+        if (a.W_red) {
+            const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W_red + (size_t)ka * a.nu, 4u * a.nu);
+            const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W_red + (size_t)kb * a.nu, 4u * a.nu);
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                v[i].x *= row_load<float>(wa, 64 * i + lane);
+                v[i].y *= row_load<float>(wb, 64 * i + lane);
+            }
+        }
+        if (a.W) {
+            const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W + (size_t)ia * a.nu, 4u * a.nu);
+            const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W + (size_t)ib * a.nu, 4u * a.nu);
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                v[i].x *= row_load<float>(wa, 64 * i + lane);
+                v[i].y *= row_load<float>(wb, 64 * i + lane);
+            }
+        }
+        dft32<-1>(v);
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            buf[k * TS + lane] = cmul(v[rev5(k)], w2048(tw, lane * k));
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < 32; ++m)
+            v[m] = buf[c * TS + 2 * m + p];
+        dft32<-1>(v);
+        // Per output d (held bit-reversed at v[rev5(d)]): X[c + 32 (d + 32 p)] =
+        // E[d] +- w64^d O[d], times the symmetrised response; then the inverse's
+        // first step, (X0 + (-1)^q X1) w64^(-q d) with q = p, stored in natural
+        // order at v[d].  Bit reversal pairs d with rev5(d), so both entries of a
+        // pair are read before either is written.
+        auto mid = [&](int d, float2 g) {
+            const float2 w = tw[32 * d];
+            const float2 mine = p ? cmul(g, w) : g;
+            const float2 other = xor1(mine);
+            const float2 x = p ? csub(other, mine) : cadd(mine, other);
+            const int k = c + 32 * d + 1024 * p;
+            const float kf = ks[k <= 1024 ? k : 2048 - k];
+            const float2 f = make_float2(x.x * kf, x.y * kf);
+            const float2 of = xor1(f);
+            const float2 sq = p ? csub(of, f) : cadd(f, of);
+            return p ? cmul(sq, make_float2(w.x, -w.y)) : sq;
+        };
+#pragma unroll
+        for (int d = 0; d < 32; ++d) {
+            const int r = rev5(d);
+            if (r > d) {
+                const float2 gd = v[r], gr = v[d];
+                v[d] = mid(d, gd);
+                v[r] = mid(r, gr);
+            } else if (r == d) {
+                v[d] = mid(d, v[d]);
+            }
+        }
+        dft32<1>(v);
+        wave_sync();   // the forward transpose has been read
+#pragma unroll
+        for (int be = 0; be < 32; ++be) {
+            const int b = 2 * be + p;
+            const float2 w = w2048(tw, b * c);
+            buf[b * US + c] = cmul(v[rev5(be)], make_float2(w.x, -w.y));
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            v[k] = buf[lane * US + k];
+        dft32<1>(v);
+        // n < nu is kept (stores past the row's end, or to an absent row b,
+        // are dropped by the buffer range check)
+        const __amdgpu_buffer_rsrc_t oa = row_rsrc(out + (size_t)ra * a.nu, 4u * a.nu);
+        const __amdgpu_buffer_rsrc_t ob = row_rsrc(out + (size_t)rb * a.nu * has_b, has_b ? 4u * a.nu : 0u);
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const float2 y = v[rev5(i)];
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x * inv), oa, (64 * i + lane) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y * inv), ob, (64 * i + lane) * 4, 0, 0);
+        }
+        wave_sync();   // the inverse transpose has been read before the next pair writes
+    }
+}
+
 template <typename T, int M>
 hipError_t wf_m(const FilterArgs &a, const void *in, float *out, hipStream_t s)
 {
@@ -88,6 +326,19 @@ hipError_t wf_m(const FilterArgs &a, const void *in, float *out, hipStream_t s)
     const long max_groups = 256L * 8;   // enough resident workgroups for 256 CUs
     const unsigned grid = (unsigned)(pairs < max_groups ? pairs : max_groups);
     hipLaunchKernelGGL((weight_filter_kernel<T, M>), dim3(grid), dim3(WF_THREADS), lds, s, a, (const T *)in, out,
+                       rows);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t s)
+{
+    const long rows = (long)a.batch * a.n_proj * a.nv;
+    const long pairs = (rows + 1) / 2;
+    const long groups = (pairs + w2k::WAVES - 1) / w2k::WAVES;
+    const long max_groups = 256L * 2;   // two resident workgroups per CU (LDS-bound)
+    const unsigned grid = (unsigned)(groups < max_groups ? groups : max_groups);
+    hipLaunchKernelGGL((weight_filter_2048_kernel<T>), dim3(grid), dim3(w2k::WAVES * 64), 0, s, a, (const T *)in, out,
                        rows);
     return hipGetLastError();
 }
@@ -103,7 +354,7 @@ hipError_t wf(const FilterArgs &a, const void *in, float *out, hipStream_t s)
     case 8: return wf_m<T, 256>(a, in, out, s);
     case 9: return wf_m<T, 512>(a, in, out, s);
     case 10: return wf_m<T, 1024>(a, in, out, s);
-    case 11: return wf_m<T, 2048>(a, in, out, s);
+    case 11: return wf_2048<T>(a, in, out, s);
     case 12: return wf_m<T, 4096>(a, in, out, s);
     default: return hipErrorInvalidValue;
     }
