@@ -91,11 +91,10 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
 // steps backwards, and lane b ends with y[64 a + b], of which n < nu is kept.
 namespace w2k {
 
-constexpr int WAVES = 4;
-constexpr int TS = 65;          // forward transpose [c][b], row stride (float2): conflict-free b64 accesses
+constexpr int WAVES = 8;         // one workgroup per CU (LDS-bound), two waves per SIMD
+constexpr int TS = 65;          // forward transpose [c][b] and twiddle table [k][b], row stride (float2)
 constexpr int US = 33;          // inverse transpose [b][c], row stride (float2)
 constexpr int BUF = 64 * US;    // float2 per wave (>= 32 * TS)
-constexpr int KS = 1028;        // symmetrised response k = 0..1024 (floats, padded)
 
 __device__ constexpr int rev5(int k)
 {
@@ -167,13 +166,6 @@ template <> __device__ __forceinline__ float row_load<bf16_t>(__amdgpu_buffer_rs
     return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, j * 2, 0, 0) << 16);
 }
 
-// exp(-2 pi i t / 2048) for t in [0, 2048) from the half table
-__device__ __forceinline__ float2 w2048(const float2 *tw, int t)
-{
-    const float2 w = tw[t & 1023];
-    return t & 1024 ? make_float2(-w.x, -w.y) : w;
-}
-
 // orders the wave's LDS writes before its lanes read each other's values
 __device__ __forceinline__ void wave_sync()
 {
@@ -189,17 +181,27 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
                                                                              float *__restrict__ out, long rows)
 {
     using namespace w2k;
-    __shared__ float2 lds[1024 + KS / 2 + WAVES * BUF];
-    float2 *tw = lds;                                   // [1024]
-    float *ks = (float *)(lds + 1024);                  // [KS]
-    float2 *buf = lds + 1024 + KS / 2 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
-    for (int n = threadIdx.x; n < 1024; n += WAVES * 64)
-        tw[n] = a.tw[n];
-    for (int n = threadIdx.x; n <= 1024; n += WAVES * 64)
-        ks[n] = 0.5f * (a.K[n] + a.K[(2048 - n) & 2047]);
+    // twt[k TS + b] = w2048^(k b) for k < 32, b < 64: every twiddle of the
+    // pair is read at an offset fixed at compile time from a per-lane base
+    __shared__ float2 lds[32 * TS + WAVES * BUF];
+    float2 *twt = lds;
+    float2 *buf = lds + 32 * TS + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
+    for (int n = threadIdx.x; n < 32 * 64; n += WAVES * 64)
+        twt[(n >> 6) * TS + (n & 63)] = a.tw[(n >> 6) * (n & 63)];   // k b < 2048
     __syncthreads();
     const float inv = 1.0f / 2048.0f;
     const long pairs = (rows + 1) / 2;
+    // the symmetrised response at this lane's middle-step outputs
+    // k = c + 32 d + 1024 p, d = 0..31 (fixed across pairs, kept in registers)
+    float kr[32];
+    {
+        const int lc = (threadIdx.x & 63) >> 1, lp = threadIdx.x & 1;
+#pragma unroll
+        for (int d = 0; d < 32; ++d) {
+            const int k = lc + 32 * d + 1024 * lp;
+            kr[d] = 0.5f * (a.K[k] + a.K[(2048 - k) & 2047]);
+        }
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
     for (long pr = (long)blockIdx.x * WAVES + wave; pr < pairs; pr += (long)gridDim.x * WAVES) {
         const long ra = 2 * pr, rb = ra + 1;
@@ -256,7 +258,7 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         dft32<-1>(v);
 #pragma unroll
         for (int k = 0; k < 32; ++k)
-            buf[k * TS + lane] = cmul(v[rev5(k)], w2048(tw, lane * k));
+            buf[k * TS + lane] = k == 0 ? v[rev5(0)] : cmul(v[rev5(k)], twt[k * TS + lane]);
         wave_sync();
 #pragma unroll
         for (int m = 0; m < 32; ++m)
@@ -267,17 +269,18 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         // first step, (X0 + (-1)^q X1) w64^(-q d) with q = p, stored in natural
         // order at v[d].  Bit reversal pairs d with rev5(d), so both entries of a
         // pair are read before either is written.
+        // twt[d TS + 32 p] is w64^d for p = 1 and 1 for p = 0, and s = (-1)^p, so
+        // every lane runs the same instructions.
+        const float sg = 1.0f - 2.0f * (float)p;
         auto mid = [&](int d, float2 g) {
-            const float2 w = tw[32 * d];
-            const float2 mine = p ? cmul(g, w) : g;
+            const float2 w = twt[d * TS + 32 * p];
+            const float2 mine = cmul(g, w);
             const float2 other = xor1(mine);
-            const float2 x = p ? csub(other, mine) : cadd(mine, other);
-            const int k = c + 32 * d + 1024 * p;
-            const float kf = ks[k <= 1024 ? k : 2048 - k];
-            const float2 f = make_float2(x.x * kf, x.y * kf);
+            const float2 x = make_float2(fmaf(sg, mine.x, other.x), fmaf(sg, mine.y, other.y));
+            const float2 f = make_float2(x.x * kr[d], x.y * kr[d]);
             const float2 of = xor1(f);
-            const float2 sq = p ? csub(of, f) : cadd(f, of);
-            return p ? cmul(sq, make_float2(w.x, -w.y)) : sq;
+            const float2 sq = make_float2(fmaf(sg, f.x, of.x), fmaf(sg, f.y, of.y));
+            return cmul(sq, make_float2(w.x, -w.y));
         };
 #pragma unroll
         for (int d = 0; d < 32; ++d) {
@@ -295,7 +298,7 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
 #pragma unroll
         for (int be = 0; be < 32; ++be) {
             const int b = 2 * be + p;
-            const float2 w = w2048(tw, b * c);
+            const float2 w = twt[c * TS + b];
             buf[b * US + c] = cmul(v[rev5(be)], make_float2(w.x, -w.y));
         }
         wave_sync();
@@ -336,7 +339,7 @@ hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t 
     const long rows = (long)a.batch * a.n_proj * a.nv;
     const long pairs = (rows + 1) / 2;
     const long groups = (pairs + w2k::WAVES - 1) / w2k::WAVES;
-    const long max_groups = 256L * 2;   // two resident workgroups per CU (LDS-bound)
+    const long max_groups = 256;        // one resident workgroup per CU (LDS-bound)
     const unsigned grid = (unsigned)(groups < max_groups ? groups : max_groups);
     hipLaunchKernelGGL((weight_filter_2048_kernel<T>), dim3(grid), dim3(w2k::WAVES * 64), 0, s, a, (const T *)in, out,
                        rows);
