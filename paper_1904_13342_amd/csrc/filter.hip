@@ -189,7 +189,6 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
     for (int n = threadIdx.x; n < 32 * 64; n += WAVES * 64)
         twt[(n >> 6) * TS + (n & 63)] = a.tw[(n >> 6) * (n & 63)];   // k b < 2048
     __syncthreads();
-    const float inv = 1.0f / 2048.0f;
     const long pairs = (rows + 1) / 2;
     // the symmetrised response at this lane's middle-step outputs
     // k = c + 32 d + 1024 p, d = 0..31 (fixed across pairs, kept in registers)
@@ -223,18 +222,31 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         // the weights, one wave-uniform pass per factor present
         const int ia = (int)(ra % a.nv), ka = (int)((ra / a.nv) % a.n_proj);
         const int ib = (int)(rb % a.nv), kb = (int)((rb / a.nv) % a.n_proj);
-        if (a.cos_sdd > 0.0f && a.curved) {   // cos(gamma_j), the same for both rows
+        // Cosine weights (Kak & Slaney) with u_j = (j - cu) du: on the arc
+        // cos(u_j / SDD), the same for both rows (the hardware cosine takes
+        // revolutions); on a flat detector SDD / sqrt(SDD^2 + u_j^2 + v_i^2),
+        // whose factor SDD is applied with the output scale.
+        float oscale = 1.0f / 2048.0f;
+        if (a.cos_sdd > 0.0f && a.curved) {
+            const float rev = 1.0f / (a.cos_sdd * 6.283185307f);
+            const float g0 = ((float)lane - a.cu) * a.du * rev, gs = 64.0f * a.du * rev;
 #pragma unroll
             for (int i = 0; i < 32; ++i) {
-                const float w = cosine_weight(a, ia, 64 * i + lane);
+                const float w = __builtin_amdgcn_cosf(fmaf((float)i, gs, g0));
                 v[i].x *= w;
                 v[i].y *= w;
             }
         } else if (a.cos_sdd > 0.0f) {
+            const float va = ((float)ia - a.cv) * a.dv, vb = ((float)ib - a.cv) * a.dv;
+            const float s2 = a.cos_sdd * a.cos_sdd;
+            const float ca = fmaf(va, va, s2), cb = fmaf(vb, vb, s2);
+            const float u0 = ((float)lane - a.cu) * a.du, us = 64.0f * a.du;
+            oscale *= a.cos_sdd;
 #pragma unroll
             for (int i = 0; i < 32; ++i) {
-                v[i].x *= cosine_weight(a, ia, 64 * i + lane);
-                v[i].y *= cosine_weight(a, ib, 64 * i + lane);
+                const float u = fmaf((float)i, us, u0), uu = u * u;
+                v[i].x *= __builtin_amdgcn_rsqf(uu + ca);
+                v[i].y *= __builtin_amdgcn_rsqf(uu + cb);
             }
         }
         if (a.W_red) {
@@ -313,8 +325,8 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
 #pragma unroll
         for (int i = 0; i < 32; ++i) {
             const float2 y = v[rev5(i)];
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x * inv), oa, (64 * i + lane) * 4, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y * inv), ob, (64 * i + lane) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x * oscale), oa, (64 * i + lane) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y * oscale), ob, (64 * i + lane) * 4, 0, 0);
         }
         wave_sync();   // the inverse transpose has been read before the next pair writes
     }
