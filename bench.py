@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 # packed math; HBM3E 8 TB/s.
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 39.3 T lane-ops/s
 PEAK_HBM_GBS = 8000.0
-# Algorithmic lane-ops per unit of work (kernel table).
+# Algorithmic lane-ops per unit of work: the operations the interpolation itself needs.
 OPS_PER_UPDATE = 11.0      # back-projection: v coordinate, floor/fract, 3 lerps, accumulate
 OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7 lerps, accumulate
 
@@ -546,8 +546,8 @@ def precision_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); see DESIGN.md for how the path "
-              "would shard across GPUs.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): each GPU would run this same path "
+              "on its own share of the views (projections) or z-slabs (volume).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "corrector":
         corrector_main(args)
