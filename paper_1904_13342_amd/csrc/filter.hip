@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
 // steps backwards, and lane b ends with y[64 a + b], of which n < nu is kept.
 namespace w2k {
 
-constexpr int WAVES = 8;         // one workgroup per CU (LDS-bound), two waves per SIMD
+constexpr int WAVES = 8;         // at most: one workgroup per CU (LDS-bound), two waves per SIMD
 constexpr int TS = 65;          // forward transpose [c][b] and twiddle table [k][b], row stride (float2)
 constexpr int US = 33;          // inverse transpose [b][c], row stride (float2)
 constexpr int BUF = 64 * US;    // float2 per wave (>= 32 * TS)
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
     __shared__ float2 lds[32 * TS + WAVES * BUF];
     float2 *twt = lds;
     float2 *buf = lds + 32 * TS + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
-    for (int n = threadIdx.x; n < 32 * 64; n += WAVES * 64)
+    for (int n = threadIdx.x; n < 32 * 64; n += blockDim.x)
         twt[(n >> 6) * TS + (n & 63)] = a.tw[(n >> 6) * (n & 63)];   // k b < 2048
     __syncthreads();
     const long pairs = (rows + 1) / 2;
@@ -202,7 +202,8 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         }
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
-    for (long pr = (long)blockIdx.x * WAVES + wave; pr < pairs; pr += (long)gridDim.x * WAVES) {
+    const int nw = blockDim.x >> 6;   // waves in this workgroup (1 .. WAVES)
+    for (long pr = (long)blockIdx.x * nw + wave; pr < pairs; pr += (long)gridDim.x * nw) {
         const long ra = 2 * pr, rb = ra + 1;
         const bool has_b = rb < rows;
         // The lane index is made opaque per pair so that per-column terms
@@ -350,10 +351,13 @@ hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t 
 {
     const long rows = (long)a.batch * a.n_proj * a.nv;
     const long pairs = (rows + 1) / 2;
-    const long groups = (pairs + w2k::WAVES - 1) / w2k::WAVES;
-    const long max_groups = 256;        // one resident workgroup per CU (LDS-bound)
-    const unsigned grid = (unsigned)(groups < max_groups ? groups : max_groups);
-    hipLaunchKernelGGL((weight_filter_2048_kernel<T>), dim3(grid), dim3(w2k::WAVES * 64), 0, s, a, (const T *)in, out,
+    // One workgroup per CU. Few pairs spread over the CUs one wave each
+    // rather than sharing a few CUs' SIMDs; many fill eight waves per CU.
+    const long per_cu = (pairs + 255) / 256;
+    const int waves = (int)(per_cu < w2k::WAVES ? per_cu : w2k::WAVES);
+    const long groups = (pairs + waves - 1) / waves;
+    const unsigned grid = (unsigned)(groups < 256 ? groups : 256);
+    hipLaunchKernelGGL((weight_filter_2048_kernel<T>), dim3(grid), dim3(waves * 64), 0, s, a, (const T *)in, out,
                        rows);
     return hipGetLastError();
 }
