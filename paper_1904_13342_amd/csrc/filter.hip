@@ -333,6 +333,173 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
     }
 }
 
+// ----------------------------------------------------------------- M = 1024
+// The same scheme at 1024 = 32 x 32 (n = 32 a + b, k = c + 32 d): each half
+// of a wave transforms one pair of rows, lane b of the half holding
+// x[32 a + b], and the second step is a plain 32-point DFT per lane c, so no
+// lane exchange is needed.  A wave takes four consecutive rows; one buffer
+// resource covers them, and a lane's offset for a column past nu (or a row
+// past the end) lies beyond the resource, so its loads read 0 and its stores
+// are dropped.
+namespace w1k {
+
+constexpr int WAVES = 8;        // at most: one workgroup per CU (LDS-bound)
+constexpr int S = 33;           // transposes [32][33] per half-wave, twiddle table [32][33] (float2)
+constexpr int BUF = 2 * 32 * S; // float2 per wave
+constexpr int FAR = 1 << 28;    // element offset past four rows and past any weight table under 1 GiB
+
+}  // namespace w1k
+
+template <typename T>
+__global__ void __launch_bounds__(w1k::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) weight_filter_1024_kernel(
+    FilterArgs a, const T *__restrict__ in, float *__restrict__ out, long rows)
+{
+    using namespace w1k;
+    using w2k::dft32;
+    using w2k::rev5;
+    using w2k::row_load;
+    using w2k::row_rsrc;
+    using w2k::wave_sync;
+    // twt[k S + b] = w1024^(k b) for k, b < 32; ks: the symmetrised response
+    __shared__ float2 lds[32 * S + WAVES * BUF + 512];
+    float2 *twt = lds;
+    float *ks = (float *)(lds + 32 * S + WAVES * BUF);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
+    for (int n = threadIdx.x; n < 32 * 32; n += blockDim.x) {
+        twt[(n >> 5) * S + (n & 31)] = a.tw[(n >> 5) * (n & 31)];   // k b < 1024
+        ks[n] = 0.5f * (a.K[n] + a.K[(1024 - n) & 1023]);
+    }
+    __syncthreads();
+    const long quads = (rows + 3) / 4;
+    const int nw = blockDim.x >> 6;   // waves in this workgroup (1 .. WAVES)
+    for (long qd = (long)blockIdx.x * nw + wave; qd < quads; qd += (long)gridDim.x * nw) {
+        int lane = threadIdx.x & 63;
+        asm volatile("" : "+v"(lane));   // per-column terms recomputed, not hoisted and spilled
+        const int h = lane >> 5, l = lane & 31;
+        float2 *buf = lds + 32 * S + wave * BUF + h * 32 * S;
+        const long r0 = 4 * qd;
+        const int nrows = (int)(rows - r0 < 4 ? rows - r0 : 4);
+        // this half's rows r0 + 2h (real part) and r0 + 2h + 1 (imaginary part):
+        // detector row i and view k of each, from those of r0
+        const int i0 = (int)(r0 % a.nv), k0 = (int)((r0 / a.nv) % a.n_proj);
+        int ia = i0 + 2 * h, ka = k0;
+        while (ia >= a.nv) {
+            ia -= a.nv;
+            ka = ka + 1 == a.n_proj ? 0 : ka + 1;
+        }
+        int ib = ia + 1, kb = ka;
+        if (ib == a.nv) {
+            ib = 0;
+            kb = kb + 1 == a.n_proj ? 0 : kb + 1;
+        }
+        const __amdgpu_buffer_rsrc_t rin = row_rsrc(in + (size_t)r0 * a.nu, (unsigned)nrows * a.nu * (unsigned)sizeof(T));
+        const int ea = 2 * h * a.nu, eb = ea + a.nu;   // element offsets of the two rows
+        float2 v[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const int n = 32 * i + l;
+            const bool in_row = n < a.nu;
+            v[i] = make_float2(row_load<T>(rin, in_row ? ea + n : FAR), row_load<T>(rin, in_row ? eb + n : FAR));
+        }
+        float oscale = 1.0f / 1024.0f;
+        if (a.cos_sdd > 0.0f && a.curved) {
+            const float rev = 1.0f / (a.cos_sdd * 6.283185307f);
+            const float g0 = ((float)l - a.cu) * a.du * rev, gs = 32.0f * a.du * rev;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const float w = __builtin_amdgcn_cosf(fmaf((float)i, gs, g0));
+                v[i].x *= w;
+                v[i].y *= w;
+            }
+        } else if (a.cos_sdd > 0.0f) {
+            const float va = ((float)ia - a.cv) * a.dv, vb = ((float)ib - a.cv) * a.dv;
+            const float s2 = a.cos_sdd * a.cos_sdd;
+            const float ca = fmaf(va, va, s2), cb = fmaf(vb, vb, s2);
+            const float u0 = ((float)l - a.cu) * a.du, us = 32.0f * a.du;
+            oscale *= a.cos_sdd;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const float u = fmaf((float)i, us, u0), uu = u * u;
+                v[i].x *= __builtin_amdgcn_rsqf(uu + ca);
+                v[i].y *= __builtin_amdgcn_rsqf(uu + cb);
+            }
+        }
+        if (a.W_red) {
+            const __amdgpu_buffer_rsrc_t wr = row_rsrc(a.W_red, 4u * (unsigned)a.n_proj * a.nu);
+            const int wa = ka * a.nu, wb = kb * a.nu;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int n = 32 * i + l;
+                const bool in_row = n < a.nu;
+                v[i].x *= row_load<float>(wr, in_row ? wa + n : FAR);
+                v[i].y *= row_load<float>(wr, in_row ? wb + n : FAR);
+            }
+        }
+        if (a.W) {
+            const __amdgpu_buffer_rsrc_t wl = row_rsrc(a.W, 4u * (unsigned)a.nv * a.nu);
+            const int wa = ia * a.nu, wb = ib * a.nu;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int n = 32 * i + l;
+                const bool in_row = n < a.nu;
+                v[i].x *= row_load<float>(wl, in_row ? wa + n : FAR);
+                v[i].y *= row_load<float>(wl, in_row ? wb + n : FAR);
+            }
+        }
+        // forward: 32-point DFTs over a (lane b), twiddles w1024^(b c), transpose,
+        // 32-point DFTs over b (lane c): X[c + 32 d] at v[rev5(d)]
+        dft32<-1>(v);
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            buf[k * S + l] = k == 0 ? v[rev5(0)] : cmul(v[rev5(k)], twt[k * S + l]);
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < 32; ++m)
+            v[m] = buf[l * S + m];
+        dft32<-1>(v);
+        // times the symmetrised response, put in natural order over d in
+        // place (bit reversal pairs d with rev5(d))
+        const float *kc = ks + l;   // K_s[c + 32 d] = kc[32 d]
+#pragma unroll
+        for (int d = 0; d < 32; ++d) {
+            const int r = rev5(d);
+            if (r > d) {
+                const float2 gd = v[r], gr = v[d];
+                const float kd = kc[32 * d], kq = kc[32 * r];
+                v[d] = make_float2(gd.x * kd, gd.y * kd);
+                v[r] = make_float2(gr.x * kq, gr.y * kq);
+            } else if (r == d) {
+                const float kd = kc[32 * d];
+                v[d] = make_float2(v[d].x * kd, v[d].y * kd);
+            }
+        }
+        // inverse: 32-point DFTs over d (lane c), twiddles w1024^(-b c),
+        // transpose, 32-point DFTs over c (lane b): y[32 a + b] at v[rev5(a)]
+        dft32<1>(v);
+        wave_sync();   // the forward transpose has been read
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+            const float2 w = twt[l * S + b];
+            buf[b * S + l] = cmul(v[rev5(b)], make_float2(w.x, -w.y));
+        }
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+            v[c] = buf[l * S + c];
+        dft32<1>(v);
+        const __amdgpu_buffer_rsrc_t ro = row_rsrc(out + (size_t)r0 * a.nu, (unsigned)nrows * a.nu * 4u);
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const int n = 32 * i + l;
+            const bool in_row = n < a.nu;
+            const float2 y = v[rev5(i)];
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x * oscale), ro, (in_row ? ea + n : FAR) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y * oscale), ro, (in_row ? eb + n : FAR) * 4, 0, 0);
+        }
+        wave_sync();   // the inverse transpose has been read before the next rows are written
+    }
+}
+
 template <typename T, int M>
 hipError_t wf_m(const FilterArgs &a, const void *in, float *out, hipStream_t s)
 {
@@ -363,6 +530,23 @@ hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t 
 }
 
 template <typename T>
+hipError_t wf_1024(const FilterArgs &a, const void *in, float *out, hipStream_t s)
+{
+    // weight tables are addressed by 32-bit offsets from one resource
+    if ((size_t)a.n_proj * a.nu * 4 >= ((size_t)w1k::FAR) * 4 || (size_t)a.nv * a.nu * 4 >= ((size_t)w1k::FAR) * 4)
+        return wf_m<T, 1024>(a, in, out, s);
+    const long rows = (long)a.batch * a.n_proj * a.nv;
+    const long quads = (rows + 3) / 4;
+    const long per_cu = (quads + 255) / 256;
+    const int waves = (int)(per_cu < w1k::WAVES ? per_cu : w1k::WAVES);
+    const long groups = (quads + waves - 1) / waves;
+    const unsigned grid = (unsigned)(groups < 256 ? groups : 256);
+    hipLaunchKernelGGL((weight_filter_1024_kernel<T>), dim3(grid), dim3(waves * 64), 0, s, a, (const T *)in, out,
+                       rows);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t wf(const FilterArgs &a, const void *in, float *out, hipStream_t s)
 {
     switch (a.log2M) {
@@ -372,7 +556,7 @@ hipError_t wf(const FilterArgs &a, const void *in, float *out, hipStream_t s)
     case 7: return wf_m<T, 128>(a, in, out, s);
     case 8: return wf_m<T, 256>(a, in, out, s);
     case 9: return wf_m<T, 512>(a, in, out, s);
-    case 10: return wf_m<T, 1024>(a, in, out, s);
+    case 10: return wf_1024<T>(a, in, out, s);
     case 11: return wf_2048<T>(a, in, out, s);
     case 12: return wf_m<T, 4096>(a, in, out, s);
     default: return hipErrorInvalidValue;
