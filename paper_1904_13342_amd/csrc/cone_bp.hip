@@ -278,24 +278,25 @@ __device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su
         unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j + 1, b * fu);
 }
 
-__device__ __forceinline__ void zero_tile(double *tile, const Footprint &fp, int tid)
+// The tile is cleared once per workgroup; each flush then reads and clears
+// the footprint it adds to the projections (splats never leave the
+// footprint), so the tile is zero again whenever the next view starts.
+__device__ __forceinline__ void clear_tile(double *tile, int tid)
 {
-    for (int r = tid >> 4; r < fp.th; r += 16)
-        for (int c = tid & 15; c < fp.tw; c += 16)
-            tile[r * BPT_TS + c] = 0.0;
+    for (int n = tid; n < BP_TH * BPT_TS; n += 256)
+        tile[n] = 0.0;
 }
 
-__device__ __forceinline__ void flush_tile(const double *tile, const Footprint &fp, const Geom3D &g, float *qk,
-                                           int tid)
+__device__ __forceinline__ void flush_tile(double *tile, const Footprint &fp, const Geom3D &g, float *qk, int tid)
 {
     for (int r = tid >> 4; r < fp.th; r += 16) {
         const int gi = fp.v_lo + r;
-        if ((unsigned)gi >= (unsigned)g.nv)
-            continue;
+        const bool row_ok = (unsigned)gi < (unsigned)g.nv;
         for (int c = tid & 15; c < fp.tw; c += 16) {
             const int gj = fp.u_lo + c;
             const float t = (float)tile[r * BPT_TS + c];
-            if (t != 0.0f && (unsigned)gj < (unsigned)g.nu)
+            tile[r * BPT_TS + c] = 0.0;
+            if (t != 0.0f && row_ok && (unsigned)gj < (unsigned)g.nu)
                 unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
         }
     }
@@ -329,6 +330,7 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
     float val[4][ZQ];
     int cur = -1;   // lane layout of val: 0 = lanes along y, 1 = lanes along x
+    clear_tile(tile, tid);   // ordered before the first splat by the view loop's barrier
 
     for (int k = 0; k < g.n_proj; ++k) {
         const ConeBPView v = views[k];
@@ -352,11 +354,8 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
         const Footprint fp = brick_footprint(v, g, cx, cy, cz);
         const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
         float *qk = pb + (size_t)k * g.nv * g.nu;
-        if (staged) {
-            __syncthreads();   // the previous tile has been flushed
-            zero_tile(tile, fp, tid);
-            __syncthreads();
-        }
+        if (staged)
+            __syncthreads();   // the previous tile has been flushed and cleared
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int ix = bxi * 16 + (orient == 0 ? 4 * wave + c : a);
@@ -429,17 +428,15 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
     for (int z = 0; z < BP_NZ; ++z)
         val[z] = (active && z < zcount) ? g.dbeta * load_f32(src + (size_t)(z0 + z) * g.ny * g.nx) : 0.0f;
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
+    clear_tile(tile, tid);   // ordered before the first splat by the view loop's barrier
 
     for (int k = 0; k < g.n_proj; ++k) {
         const ConeBPView v = views[k];
         const Footprint fp = brick_footprint(v, g, cx, cy, cz);
         const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
         float *qk = pb + (size_t)k * g.nv * g.nu;
-        if (staged) {
-            __syncthreads();
-            zero_tile(tile, fp, tid);
-            __syncthreads();
-        }
+        if (staged)
+            __syncthreads();   // the previous tile has been flushed and cleared
         if (active) {
 #pragma unroll
             for (int z = 0; z < BP_NZ; ++z) {
