@@ -101,22 +101,20 @@ __device__ __forceinline__ void make_ray_2d(const Geom2D &g, float2 c, int j, fl
 // in a fan view with central ray c: central projection onto the flat detector
 // with weight (SID / w)^2, w the depth along the central ray; on the
 // equiangular detector the bin of the pixel's fan angle, with weight
-// (SID / L)^2, L the distance from the source.  For the equiangular detector
-// the pixel position, its fan angle, bin and fraction are formed in double
-// precision (in FP32 the position and the arctangent alone misplace wide-fan
-// samples by a few 1e-6 bin).  The back-projector and its transpose both use
-// this, so they see the same coordinates.
+// (SID / L)^2, L the distance from the source.  All in FP32: the arctangent
+// places a wide fan's samples to a few 1e-6 bin.  The back-projector and its
+// transpose both use this, so they see the same coordinates.
 __device__ __forceinline__ void fan2d_point(const Geom2D &g, float2 c, int ix, int iy, int &j, float &t, float &wt)
 {
     if (g.curved) {
-        const double x = fma((double)ix, (double)g.sx, (double)g.ox), y = fma((double)iy, (double)g.sy, (double)g.oy);
-        const double xu = fma(y, (double)c.x, -x * (double)c.y);
-        const double w = fma(x, (double)c.x, fma(y, (double)c.y, (double)g.sid));
-        const double s = fma(atan2(xu, w), (double)g.sdd / (double)g.du, (double)g.cu);
-        const double fs = floor(s);
+        const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
+        const float xu = -x * c.y + y * c.x;
+        const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
+        const float s = fmaf(atan2f(xu, w), g.sdd / g.du, g.cu);
+        const float fs = floorf(s);
         j = (int)fs;
-        t = (float)(s - fs);
-        wt = (float)((double)g.sid * (double)g.sid / fma(w, w, xu * xu));
+        t = s - fs;
+        wt = g.sid * g.sid / fmaf(w, w, xu * xu);
     } else {
         const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
         const float xu = -x * c.y + y * c.x;
