@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
     float acc = 0.0f;
     if (krange(X0, eX, g.nx, lo, hi) && krange(Y0, eY, g.ny, lo, hi) && lo < hi) {
         const int k0 = (int)floorf(lo) - 1, k1 = (int)ceilf(hi) + 1;
+#pragma unroll 4   // several samples' loads in flight at once
         for (int m = k0 + s; m <= k1; m += S) {
             const float fm = (float)m;
             const float X = fmaf(fm, eX, X0), Y = fmaf(fm, eY, Y0);
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__res
     const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
     const float rdu = 1.0f / g.du;
     float acc = 0.0f;
+#pragma unroll 4   // several views' loads in flight at once
     for (int k = 0; k < g.n_proj; ++k) {
         const float2 c = views[k];
         int j;
