@@ -2,14 +2,19 @@
 // (Eq. 4 / Eq. 5; the filter is a diagonal multiply in the Fourier domain,
 // Sec. II.C.4; the weights are Sec. II.C.5's cosine and redundancy weights).
 //
-// A workgroup transforms two detector rows at once: row a goes into the real
-// part and row b into the imaginary part of one complex M-point sequence.
-// The response is real and even (it is symmetrised first), so the inverse
+// Two detector rows are transformed at once: row a goes into the real part
+// and row b into the imaginary part of one complex M-point sequence.  The
+// response is real and even (it is symmetrised first), so the inverse
 // transform of K . DFT(a + i b) is (K * a) + i (K * b): both filtered rows come
-// out of one forward / inverse pair.  The transforms are in-place Stockham
-// radix-8 passes (radix 4 or 2 for the last one) in LDS with the butterflies
-// in registers, natural order in and out.  Workgroups loop over row pairs
-// (grid sized to the machine) with the twiddle half-table held in LDS.
+// out of one forward / inverse pair.
+//
+// M = 2048 and M = 1024 (the lengths of every workload here) take one wave, or
+// half a wave, per pair: a four-step transform with 32-point DFTs in registers
+// and wave-private LDS transposes (weight_filter_2048_kernel,
+// weight_filter_1024_kernel below).  Other lengths take a workgroup per pair:
+// in-place Stockham radix-8 passes (radix 4 or 2 for the last one) in LDS with
+// the butterflies in registers, natural order in and out, the twiddle
+// half-table held in LDS.  Both loop over pairs on a grid sized to the machine.
 #include "fft.h"
 
 namespace ph {
