@@ -8,7 +8,7 @@ ones their row grouping and range-checked loads and stores must get right:
 * fewer row pairs than the waves of one workgroup;
 * more than the persistent grid has waves, so every wave takes several;
 * rows as wide as the transform under a learned response, where every element
-  a lane holds is live;
+  a lane holds is live, and rows of a single bin;
 * ragged widths;
 * both weight tables present;
 * a batch of two;
@@ -50,6 +50,8 @@ CASES_3D = {
     "1024_full_width_learned": (_cone(3, 3, 1024), 1024, 1),
     "1024_ramlak": (_cone(5, 7, 500), 0, 1),
     "1024_more_groups_than_waves": (_cone(11, 751, 300), 1024, 1),
+    "1024_single_bin_last_group_one_row": (_cone(1, 5, 1), 1024, 1),
+    "2048_single_bin_odd_rows": (_cone(3, 1, 1), 2048, 1),
 }
 
 
