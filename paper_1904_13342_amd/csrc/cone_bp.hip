@@ -249,7 +249,9 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
 // instruction then hits 64 distinct pixels whenever neighbouring columns
 // project at least a pixel apart.
 
-constexpr int BPT_TS = BP_TW + 1;   // tile row stride (FP64 cells): rows start in different banks
+// tile row stride (FP64 cells, >= BP_TW + 1): 160 dwords, so consecutive rows
+// start in opposite halves of the banks (measured fastest of 65, 66, 68, 72, 80)
+constexpr int BPT_TS = 80;
 
 __device__ __forceinline__ void splat_tile(double *p, float x, float fu, float fv, int stride)
 {
