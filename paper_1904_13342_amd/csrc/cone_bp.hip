@@ -24,7 +24,7 @@ namespace {
 
 constexpr int BP_TW = 64;    // max staged footprint width (detector columns)
 constexpr int BP_TH = 120;   // max staged footprint height (detector rows)
-constexpr int BP_TS = 65;    // tile row stride: rows start in different LDS banks
+constexpr int BP_TS = 66;    // tile row stride: 66 measured fastest of 65-68 (five workgroups per CU)
 
 template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
