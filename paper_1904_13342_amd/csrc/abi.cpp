@@ -266,7 +266,7 @@ void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
 }
 
 // Deeper column segment (32 or 16 voxels) whose 16 x 16 x NZ brick
-// footprint fits the back-projector's 64 x 128 pixel LDS tile, from a bound on
+// footprint fits the back-projector's 64 x 102 pixel LDS tile, from a bound on
 // the magnification (nearest approach of a voxel to the source) and on the
 // row slope across a brick at the top and bottom of the volume.
 int bp_segment(const ph_geom3d *g)
@@ -285,7 +285,7 @@ int bp_segment(const ph_geom3d *g)
     const double slope = zmax * g->sdd / g->det_spacing[0] * brick / (wmin * wmin);
     for (int nz = 32; nz >= 32; nz /= 2) {
         const double th = nz * sz * mag / g->det_spacing[0] + slope + 4.0;
-        if (tw <= 64.0 && th <= 120.0)
+        if (tw <= 64.0 && th <= 102.0)   // the back-projector's LDS tile: 64 x 102 pixels
             return nz;
     }
     return 16;

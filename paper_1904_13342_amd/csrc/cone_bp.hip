@@ -23,8 +23,10 @@ namespace ph {
 namespace {
 
 constexpr int BP_TW = 64;    // max staged footprint width (detector columns)
-constexpr int BP_TH = 120;   // max staged footprint height (detector rows)
-constexpr int BP_TS = 66;    // tile row stride: 66 measured fastest of 65-68 (five workgroups per CU)
+constexpr int BP_TH = 102;   // max staged footprint height (detector rows)
+// Tile row stride: 78 floats measured fastest of 65-68, 70, 74, 78, 82 and 90,
+// each with the largest height that keeps five workgroups per CU.
+constexpr int BP_TS = 78;
 
 template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
