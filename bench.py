@@ -44,11 +44,11 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.0, 1048580.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.3232e7, "write_kib": 1.23768e6,
+    "fp_cone": {"fetch_kib": 7.23126e7, "write_kib": 1.23831e6,
                 "sources": ("cone_fp.hip", "device_util.h"), "sha256_16": "b2b7fab7ffe28763"},
-    "bp_cone": {"fetch_kib": 8.13287e6, "write_kib": 524288.0,
-                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "77460fcf15ad2543"},
-    "weight_filter": {"fetch_kib": 564710.0, "write_kib": 1.10592e6,
+    "bp_cone": {"fetch_kib": 8.26492e6, "write_kib": 524288.0,
+                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "32130d977583f1a2"},
+    "weight_filter": {"fetch_kib": 564813.0, "write_kib": 1.10592e6,
                       "sources": ("filter.hip", "fft.h"), "sha256_16": "8b2cc952ec176687"},
 }
 
