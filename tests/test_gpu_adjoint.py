@@ -30,6 +30,7 @@ SPECS = {
                                                     det_spacing=(1.1,), n_proj=11, angular_range=250 * math.pi / 180,
                                                     sid=100.0, sdd=160.0),
     "cone_crop32": synth.config("cone3d_crop32").with_(n_proj=60),
+    "cone_tall_pixels": synth.config("cone3d_crop32").with_(det_shape=(140, 72), det_spacing=(0.2, 0.4), n_proj=90),
     "cone_ragged": synth.config("cone3d_crop32").with_(vol_shape=(23, 29, 35), vol_spacing=(1.1, 0.9, 1.0),
                                                        det_shape=(37, 41), det_spacing=(1.7, 1.5), n_proj=17,
                                                        angular_range=200 * math.pi / 180, sid=300.0, sdd=500.0),

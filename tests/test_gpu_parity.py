@@ -130,6 +130,9 @@ SPECS_3D = {
                                                   vol_origin=(-10.0, -14.0, -15.0)),
     "short64": synth.config("cone3d_256_short").with_(vol_shape=(64, 64, 64), vol_spacing=(4.0, 4.0, 4.0),
                                                       det_shape=(120, 155), det_spacing=(4.0, 4.0), n_proj=62),
+    # tall pixels: a 32-voxel column's footprint outgrows the back-projector's
+    # LDS tile, so the bricks are 16 voxels deep, staged
+    "tall_pixels": synth.config("cone3d_crop32").with_(det_shape=(140, 72), det_spacing=(0.2, 0.4), n_proj=90),
 }
 
 
