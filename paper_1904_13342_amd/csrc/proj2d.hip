@@ -68,21 +68,28 @@ __global__ void __launch_bounds__(256) fp2d_kernel(Geom2D g, const float2 *__res
         store_f32(sino + ((size_t)b * g.n_proj + k) * g.nu + j, g.step * acc);
 }
 
-template <typename T, typename TI, bool FAN>
+template <typename T, typename TI, bool FAN, int S>
 __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__restrict__ views,
                                                    const TI *__restrict__ sino, T *__restrict__ img)
 {
-    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    // S lanes share a pixel of a 16 x (16 / S) block, 64 / S lanes apart, so
+    // each run of 64 / S lanes reads adjacent pixels of one view; lane group s
+    // takes views s, s + S, ... and the partial sums meet in a fixed shuffle
+    // tree over the high lane bits
+    constexpr int PW = 64 / S;   // pixels per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = wave * PW + lane % PW, s = lane / PW;
+    const int ix = blockIdx.x * 16 + (p & 15);
+    const int iy = blockIdx.y * (16 / S) + (p >> 4);
     const int b = blockIdx.z;
     if (ix >= g.nx || iy >= g.ny)
-        return;
+        return;   // whole pixels only: the S lanes of a pixel leave together
     const TI *sb = sino + (size_t)b * g.n_proj * g.nu;
     const float x = fmaf((float)ix, g.sx, g.ox), y = fmaf((float)iy, g.sy, g.oy);
     const float rdu = 1.0f / g.du;
     float acc = 0.0f;
 #pragma unroll 4   // several views' loads in flight at once
-    for (int k = 0; k < g.n_proj; ++k) {
+    for (int k = s; k < g.n_proj; k += S) {
         const float2 c = views[k];
         int j;
         float t, wt;
@@ -100,7 +107,11 @@ __global__ void __launch_bounds__(256) bp2d_kernel(Geom2D g, const float2 *__res
         const float p1 = (j + 1 >= 0 && j + 1 < g.nu) ? load_f32(row + j + 1) : 0.0f;
         acc = fmaf(wt, fmaf(t, p1 - p0, p0), acc);
     }
-    store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.dbeta * acc);
+#pragma unroll
+    for (int o = 32; o >= PW; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if (s == 0)
+        store_f32(img + ((size_t)b * g.ny + iy) * g.nx + ix, g.dbeta * acc);
 }
 
 // lanes per work item so that a launch holds about 2^21 threads (measured
@@ -143,18 +154,35 @@ hipError_t fp2d(bool fan, const Geom2D &g, const float2 *views, const void *img,
     return fan ? fp2d_f<T, true>(g, views, img, sino, n_rays, s) : fp2d_f<T, false>(g, views, img, sino, n_rays, s);
 }
 
+template <typename T, typename TI, bool FAN, int S>
+hipError_t bp2d_s(const Geom2D &g, const float2 *views, const void *sino, void *img, int batch, hipStream_t s)
+{
+    dim3 grid((g.nx + 15) / 16, (g.ny + 16 / S - 1) / (16 / S), batch);
+    hipLaunchKernelGGL((bp2d_kernel<T, TI, FAN, S>), grid, dim3(256), 0, s, g, views, (const TI *)sino, (T *)img);
+    return hipGetLastError();
+}
+
+template <typename T, typename TI, bool FAN>
+hipError_t bp2d_f(const Geom2D &g, const float2 *views, const void *sino, void *img, int batch, hipStream_t s)
+{
+    // lanes per pixel as for the projector's rays, at least two views per lane
+    int cap = 16;
+    while (cap > 1 && 2 * cap > g.n_proj)
+        cap /= 2;
+    switch (lanes_for((long)g.nx * g.ny * batch, cap)) {
+    case 1: return bp2d_s<T, TI, FAN, 1>(g, views, sino, img, batch, s);
+    case 2: return bp2d_s<T, TI, FAN, 2>(g, views, sino, img, batch, s);
+    case 4: return bp2d_s<T, TI, FAN, 4>(g, views, sino, img, batch, s);
+    case 8: return bp2d_s<T, TI, FAN, 8>(g, views, sino, img, batch, s);
+    default: return bp2d_s<T, TI, FAN, 16>(g, views, sino, img, batch, s);
+    }
+}
+
 template <typename T, typename TI>
 hipError_t bp2d(bool fan, const Geom2D &g, const float2 *views, const void *sino, void *img, int batch,
                 hipStream_t s)
 {
-    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, batch);
-    if (fan)
-        hipLaunchKernelGGL((bp2d_kernel<T, TI, true>), grid, dim3(256), 0, s, g, views, (const TI *)sino,
-                           (T *)img);
-    else
-        hipLaunchKernelGGL((bp2d_kernel<T, TI, false>), grid, dim3(256), 0, s, g, views, (const TI *)sino,
-                           (T *)img);
-    return hipGetLastError();
+    return fan ? bp2d_f<T, TI, true>(g, views, sino, img, batch, s) : bp2d_f<T, TI, false>(g, views, sino, img, batch, s);
 }
 
 }  // namespace
