@@ -42,9 +42,12 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
     const float x0 = fmaf(fx - 1.0f, g.sx, g.ox), x1 = fmaf(fx + 1.0f, g.sx, g.ox);
     const float y0 = fmaf(fy - 1.0f, g.sy, g.oy), y1 = fmaf(fy + 1.0f, g.sy, g.oy);
     float acc = 0.0f;
+    const float rdu = __builtin_amdgcn_rcpf(g.du);
     for (int k = s; k < g.n_proj; k += S) {
         const float2 c = views[k];
         // detector bins whose rays can cross the support: project its corners
+        // (hardware reciprocals: the bin range keeps a margin of one bin below
+        // and two above)
         float smin = 3.0e38f, smax = -3.0e38f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -52,24 +55,27 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
             const float xu = -x * c.y + y * c.x;
             const float w = fmaf(x, c.x, fmaf(y, c.y, g.sid));
             // detector coordinate in mm (arc length on the equiangular detector)
-            const float su = !FAN ? xu : g.curved ? g.sdd * atan2f(xu, w) : g.sdd * xu / w;
+            const float su = !FAN ? xu : g.curved ? g.sdd * atan2f(xu, w) : g.sdd * xu * __builtin_amdgcn_rcpf(w);
             smin = fminf(smin, su);
             smax = fmaxf(smax, su);
         }
-        const int j0 = max((int)floorf(smin / g.du + g.cu) - 1, 0);
-        const int j1 = min((int)floorf(smax / g.du + g.cu) + 2, g.nu - 1);
+        const int j0 = max((int)floorf(fmaf(smin, rdu, g.cu)) - 1, 0);
+        const int j1 = min((int)floorf(fmaf(smax, rdu, g.cu)) + 2, g.nu - 1);
         for (int j = j0; j <= j1; ++j) {
             const float gv = load_f32(sb + (size_t)k * g.nu + j);
             if (gv == 0.0f)
                 continue;
             float X0, Y0, eX, eY;
             make_ray_2d<FAN>(g, c, j, X0, Y0, eX, eY);
+            // the samples that can reach the support: the clip only picks the
+            // range to visit (hardware reciprocals, widened by a sample on
+            // each side); the exact weights below decide every sample
             float lo = -3.0e38f, hi = 3.0e38f;
-            if (!clip_line(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) || !clip_line(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) ||
-                !(lo < hi))
+            if (!clip_line_rcp(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) ||
+                !clip_line_rcp(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) || !(lo < hi + 0.01f))
                 continue;
             float w = 0.0f;
-            for (int m = (int)floorf(lo); m <= (int)ceilf(hi); ++m) {
+            for (int m = (int)floorf(lo) - 1; m <= (int)ceilf(hi) + 1; ++m) {
                 const float X = fmaf((float)m, eX, X0), Y = fmaf((float)m, eY, Y0);
                 const float wx = 1.0f - fabsf(X - fx), wy = 1.0f - fabsf(Y - fy);
                 if (wx > 0.0f && wy > 0.0f)
