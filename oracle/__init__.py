@@ -54,6 +54,7 @@ class _Geom(ctypes.Structure):
         ("range", ctypes.c_double),
         ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
         ("step", ctypes.c_double),
+        ("mats", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -103,8 +104,10 @@ def _ip(a):
     return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
-def geom(spec):
-    """Oracle geometry record from a ``synth.GeometrySpec``."""
+def geom(spec, mats=None):
+    """Oracle geometry record from a ``synth.GeometrySpec``.  For a cone
+    geometry, ``mats`` ([n_proj, 3, 4], any non-zero scale per view) gives the
+    trajectory as projection matrices in place of the circular scan."""
     g = _Geom()
     g.kind = _KIND[spec.kind]
     org = spec.origin
@@ -119,6 +122,14 @@ def geom(spec):
     g.range = spec.angular_range
     g.sid, g.sdd = spec.sid, spec.sdd
     g.step = spec.step
+    if mats is not None:
+        if spec.kind != "cone3d":
+            raise ValueError("projection matrices describe cone-beam trajectories only")
+        m = np.ascontiguousarray(mats, dtype=np.float64).reshape(spec.n_proj, 12)
+        if not np.all(np.isfinite(m)) or np.any(np.abs(np.linalg.det(m.reshape(-1, 3, 4)[:, :, :3])) == 0.0):
+            raise ValueError("projection matrices must be finite with a non-singular 3x3 block")
+        g._mats = m   # keeps the array alive for as long as the record
+        g.mats = _dp(m)
     return g
 
 
@@ -149,10 +160,11 @@ def _idx(sel):
 
 # ------------------------------------------------------------------ operators
 
-def project(spec, f, views=None):
+def project(spec, f, views=None, mats=None):
     """Ray-driven forward projection A f (fixed-step multilinear sampling).
-    With ``views`` only those views are computed; the others are zero."""
-    g = geom(spec)
+    With ``views`` only those views are computed; the others are zero.
+    ``mats``: the trajectory as projection matrices (cone beams)."""
+    g = geom(spec, mats)
     f3 = _vol3(spec, f)
     p = np.zeros(_proj_shape(spec))
     v = _idx(views)
@@ -160,25 +172,25 @@ def project(spec, f, views=None):
     return _out_proj(spec, p)
 
 
-def project_adjoint(spec, p):
+def project_adjoint(spec, p, mats=None):
     """Exact transpose A^T of ``project`` (scatter)."""
-    g = geom(spec)
+    g = geom(spec, mats)
     p3 = np.ascontiguousarray(p, dtype=np.float64).reshape(_proj_shape(spec))
     f = np.zeros((g.nz, g.ny, g.nx))
     _load().ora_project_adjoint(ctypes.byref(g), _dp(p3), _dp(f))
     return _out_vol(spec, f)
 
 
-def count_samples(spec, views=None):
-    g = geom(spec)
+def count_samples(spec, views=None, mats=None):
+    g = geom(spec, mats)
     v = _idx(views)
     return int(_load().ora_count_samples(ctypes.byref(g), _ip(v), 0 if v is None else len(v)))
 
 
-def backproject(spec, q, slices=None):
+def backproject(spec, q, slices=None, mats=None):
     """Voxel-driven, distance-weighted back-projection B q.  With ``slices``
     only those z slices are computed; the others are zero."""
-    g = geom(spec)
+    g = geom(spec, mats)
     q3 = np.ascontiguousarray(q, dtype=np.float64).reshape(_proj_shape(spec))
     f = np.zeros((g.nz, g.ny, g.nx))
     s = _idx(slices)
@@ -186,9 +198,9 @@ def backproject(spec, q, slices=None):
     return _out_vol(spec, f)
 
 
-def backproject_adjoint(spec, f):
+def backproject_adjoint(spec, f, mats=None):
     """Exact transpose B^T of ``backproject`` (scatter)."""
-    g = geom(spec)
+    g = geom(spec, mats)
     f3 = _vol3(spec, f)
     q = np.zeros(_proj_shape(spec))
     _load().ora_backproject_adjoint(ctypes.byref(g), _dp(f3), _dp(q))
@@ -313,10 +325,12 @@ def filter_projections(spec, p, K=None):
     return circular_filter(p3, K)
 
 
-def fbp(spec, p, W_red=None, K=None, W=None, slices=None):
-    """FBP / FDK, Eq. 4 / Eq. 5: x = B filter(W_red W_cos p)."""
+def fbp(spec, p, W_red=None, K=None, W=None, slices=None, mats=None):
+    """FBP / FDK, Eq. 4 / Eq. 5: x = B filter(W_red W_cos p).  With ``mats``
+    the weights and the filter are those of the nominal circular geometry and
+    the back-projection follows the given projection matrices."""
     q = filter_projections(spec, weight(spec, p, W_red=W_red, W=W), K=K)
-    return backproject(spec, q, slices=slices)
+    return backproject(spec, q, slices=slices, mats=mats)
 
 
 # ------------------------------------------------------- learned corrector

@@ -26,6 +26,17 @@
  * 2D geometries are the nz = 1, z = 0 special case of the same code: with
  * z = 0 the trilinear interpolation below reduces exactly to bilinear.
  *
+ * Trajectories given as projection matrices (Sec. II.C.3: a trajectory is
+ * a set of projection matrices, as calibrated on real scanners): view k's
+ * 3x4 matrix P maps homogeneous world mm to (j*w, i*w, w), detector column j
+ * and row i.  It is first rescaled so that the 3-vector of its third row has
+ * unit length and w > 0 at the centre of the volume grid: w is then the
+ * depth in mm of a point in front of the source along the principal ray.
+ * The source is the point P sends to zero, S = -M^-1 p4 (M the left 3x3
+ * block, p4 the last column); the ray of pixel (i,j) runs along M^-1 (j,i,1);
+ * its anchor is its point closest to the world origin (the isocentre); the
+ * distance weight of the back-projector is (SID/w)^2 with the nominal SID.
+ *
  * Parity unpinned: none.  Every function is pinned by the CPU test-suite
  * against closed forms, brute force or exact invariants.
  */
@@ -48,6 +59,8 @@ typedef struct {
     double range;      /* angular range, rad */
     double sid, sdd;   /* source-isocentre and source-detector distance, mm */
     double step;       /* ray sampling step (mm) of the forward projector */
+    const double *mats; /* kind 2 only: NULL for the circular trajectory, else [n_proj][3][4]
+                           projection matrices taken as data (any non-zero scale) */
 } ora_geom;
 
 int ora_num_threads(void)
@@ -72,11 +85,64 @@ static void view_frame(const ora_geom *g, int k, double c[3], double eu[3])
     eu[2] = 0.0;
 }
 
+/* Determinant of the 3x3 block of a row-major 3x4 matrix. */
+static double det3(const double *m)
+{
+    return m[0] * (m[5] * m[10] - m[6] * m[9]) - m[1] * (m[4] * m[10] - m[6] * m[8]) +
+           m[2] * (m[4] * m[9] - m[5] * m[8]);
+}
+
+/* View k's projection matrix taken as data, rescaled: third row of the 3x3
+ * block of unit length, w > 0 at the centre of the volume grid. */
+static void view_matrix(const ora_geom *g, int k, double P[12])
+{
+    const double *m = g->mats + (size_t)k * 12;
+    const double cx = g->ox + 0.5 * (g->nx - 1) * g->sx, cy = g->oy + 0.5 * (g->ny - 1) * g->sy,
+                 cz = g->oz + 0.5 * (g->nz - 1) * g->sz;
+    double s = 1.0 / sqrt(m[8] * m[8] + m[9] * m[9] + m[10] * m[10]);
+    if (m[8] * cx + m[9] * cy + m[10] * cz + m[11] < 0.0)
+        s = -s;
+    for (int t = 0; t < 12; ++t)
+        P[t] = s * m[t];
+}
+
+/* Solution x of M x = b, M the 3x3 block of P, by Cramer's rule. */
+static void solve3(const double P[12], const double b[3], double x[3])
+{
+    double D = det3(P);
+    for (int c = 0; c < 3; ++c) {
+        double Q[12];
+        memcpy(Q, P, sizeof(Q));
+        for (int r = 0; r < 3; ++r)
+            Q[r * 4 + c] = b[r];
+        x[c] = det3(Q) / D;
+    }
+}
+
 /* Ray of detector pixel (i,j) in view k: anchor a (the point of the line
  * closest to the isocentre) and unit direction d.  Sec. II.B.2: one ray per
  * detector pixel, cast through the scene. */
 static void ray_of(const ora_geom *g, int k, int i, int j, double a[3], double d[3])
 {
+    if (g->kind == 2 && g->mats) {
+        /* source S = -M^-1 p4, direction M^-1 (j, i, 1), anchor closest to
+         * the world origin */
+        double P[12], s[3], n = 0.0, sd = 0.0;
+        view_matrix(g, k, P);
+        const double p4[3] = {-P[3], -P[7], -P[11]}, pix[3] = {(double)j, (double)i, 1.0};
+        solve3(P, p4, s);
+        solve3(P, pix, d);
+        for (int t = 0; t < 3; ++t)
+            n += d[t] * d[t];
+        n = sqrt(n);
+        for (int t = 0; t < 3; ++t) {
+            d[t] /= n;
+            sd += s[t] * d[t];
+        }
+        for (int t = 0; t < 3; ++t)
+            a[t] = s[t] - sd * d[t];
+        return;
+    }
     double c[3], eu[3];
     view_frame(g, k, c, eu);
     double u = ((double)j - 0.5 * (g->nu - 1)) * g->du;
@@ -331,6 +397,17 @@ long long ora_count_samples(const ora_geom *g, const int *views, int nviews)
  * distance of x from the source (Kak & Slaney's equiangular back-projection). */
 static void project_point(const ora_geom *g, int k, const double x[3], double *su, double *sv, double *wt)
 {
+    if (g->kind == 2 && g->mats) {
+        /* (j w, i w, w) = P [x; 1] with the rescaled matrix: w in mm */
+        double P[12], h[3];
+        view_matrix(g, k, P);
+        for (int r = 0; r < 3; ++r)
+            h[r] = P[r * 4] * x[0] + P[r * 4 + 1] * x[1] + P[r * 4 + 2] * x[2] + P[r * 4 + 3];
+        *su = h[0] / h[2];
+        *sv = h[1] / h[2];
+        *wt = (g->sid / h[2]) * (g->sid / h[2]);
+        return;
+    }
     double c[3], eu[3];
     view_frame(g, k, c, eu);
     double xu = x[0] * eu[0] + x[1] * eu[1];

@@ -19,6 +19,7 @@ from .phantom import (
 )
 from .configs import CONFIGS, config, GeometrySpec
 from .rng import random_array
+from .trajectory import perturbed_poses, pose_matrices, pixel_positions
 
 __all__ = [
     "random_ellipses",
@@ -34,4 +35,7 @@ __all__ = [
     "config",
     "GeometrySpec",
     "random_array",
+    "perturbed_poses",
+    "pose_matrices",
+    "pixel_positions",
 ]
