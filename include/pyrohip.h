@@ -120,11 +120,11 @@ int ph_projection_matrices_3d(const ph_geom3d *g, float *mats);
  *   vol  : device [batch][nz][ny][nx]    (dtype)      input
  *   proj : device [batch][n_proj][nv][nu](dtype)      output */
 int ph_project_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
-                     int dtype, void *stream);
+                     ph_dtype dtype, void *stream);
 int ph_project_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
-                     int dtype, void *stream);
+                     ph_dtype dtype, void *stream);
 int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
-                      int dtype, void *stream);
+                      ph_dtype dtype, void *stream);
 
 /* ------------------------------------------------- back-projection B
  * Sec. II.B.2 (voxel-driven back-projection: every voxel accumulates the
@@ -138,11 +138,11 @@ int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, vo
  * equiangular reconstruction).  Same arrays as the forward calls with the
  * roles of input and output exchanged. */
 int ph_backproject_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
-                         int dtype, void *stream);
+                         ph_dtype dtype, void *stream);
 int ph_backproject_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
-                         int dtype, void *stream);
+                         ph_dtype dtype, void *stream);
 int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
-                          int dtype, void *stream);
+                          ph_dtype dtype, void *stream);
 
 /* ------------------------------------------------- exact transposes
  * Sec. II.B.2: the ray-driven projector and the voxel-driven back-projector
@@ -162,30 +162,30 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
  * hence the last bits, may vary from run to run.
  *   img/vol   : device FP32 input; sino/proj : device FP32 output */
 int ph_project_adjoint_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
-                             int dtype, void *stream);
+                             ph_dtype dtype, void *stream);
 int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, int batch,
-                             int dtype, void *stream);
+                             ph_dtype dtype, void *stream);
 int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
-                              int dtype, void *stream);
+                              ph_dtype dtype, void *stream);
 int ph_backproject_adjoint_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
-                                 int dtype, void *stream);
+                                 ph_dtype dtype, void *stream);
 int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
-                                 int dtype, void *stream);
+                                 ph_dtype dtype, void *stream);
 int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
-                                  int dtype, void *stream);
+                                  ph_dtype dtype, void *stream);
 
 /* B^T with any storage type (extension 1): the scatter accumulates in FP32,
  * in the output itself for FP32 and otherwise in the workspace `ws` of
  * ph_backproject_adjoint_workspace_bytes_*() bytes (0 for FP32, where ws may
  * be NULL), which is then rounded to the storage type (nearest even). */
-size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, int dtype);
-size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, int dtype);
+size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, ph_dtype dtype);
+size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, ph_dtype dtype);
 int ph_backproject_adjoint_ws_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, void *ws,
-                                    size_t ws_bytes, int batch, int dtype, void *stream);
+                                    size_t ws_bytes, int batch, ph_dtype dtype, void *stream);
 int ph_backproject_adjoint_ws_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, void *ws,
-                                    size_t ws_bytes, int batch, int dtype, void *stream);
+                                    size_t ws_bytes, int batch, ph_dtype dtype, void *stream);
 int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws,
-                                     size_t ws_bytes, int batch, int dtype, void *stream);
+                                     size_t ws_bytes, int batch, ph_dtype dtype, void *stream);
 
 /* --------------------------------------------- weighting + ramp filtering
  * Eq. 4 / Eq. 5 without the back-projection: q = F^H K F (W_red * W_cos * W * p),
@@ -204,7 +204,7 @@ int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, cons
  *   out   : device float[batch][n_proj](nv)[nu], FP32 regardless of dtype.
  * M = 0 with K = NULL selects the default length. */
 int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
-                        const float *W_red, int batch, int dtype, void *stream);
+                        const float *W_red, int batch, ph_dtype dtype, void *stream);
 
 /* Filter responses on the M-point DFT grid for the K argument above
  * (Sec. II.C.4; Sec. III.B initialises the learned filter with the ramp).
@@ -225,7 +225,7 @@ int ph_filter_response(int kind, int M, double tau, float *K);
  * SID > 0, finite. */
 int ph_filter_response_equiangular(int M, double alpha, double sid, float *K);
 int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M,
-                        const float *W_red, const float *W, int batch, int dtype, void *stream);
+                        const float *W_red, const float *W, int batch, ph_dtype dtype, void *stream);
 
 /* ------------------------------------------------------- FBP / FDK
  * Eq. 4 (FBP) and Eq. 5 (FDK network): x = B F^H K F W_red W_cos p.
@@ -237,13 +237,18 @@ int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const 
  * filtered projections. */
 size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch);
 size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch);
+/* Workspace of ph_fdk_cone3d for filter length M (0 = the default Ram-Lak
+ * length) and storage type dtype, in bytes: the filtered projections are
+ * held in FP32 whatever M and dtype, so this equals ph_workspace_bytes_3d.
+ * Returns 0 for an invalid geometry, batch, M or dtype. */
+size_t ph_fdk_workspace_bytes(const ph_geom3d *g, int M, int batch, ph_dtype dtype);
 
 int ph_fbp_par2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, const float *K, int M,
-                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream);
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream);
 int ph_fbp_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *sino, void *img, const float *K, int M,
-                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream);
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream);
 int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
-                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, int dtype,
+                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, ph_dtype dtype,
                   void *stream);
 
 /* ------------------------------------------- learned corrector training

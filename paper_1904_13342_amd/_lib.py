@@ -86,6 +86,7 @@ SIGNATURES = {
     "ph_weight_filter_3d": (_I, [_G3, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "ph_workspace_bytes_2d": (_SZ, [_G2, _I]),
     "ph_workspace_bytes_3d": (_SZ, [_G3, _I]),
+    "ph_fdk_workspace_bytes": (_SZ, [_G3, _I, _I, _I]),
     "ph_fbp_par2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fbp_fan2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fdk_cone3d": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _P, _SZ, _I, _I, _P]),

@@ -3,6 +3,7 @@
 // per-device cache of those parameters, and kernel dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -236,8 +237,10 @@ int normalised_mats(const ph_geom3d *g, const float *mats, std::vector<double> *
 }
 
 // Back-projector rows over centred voxel indices, and whether the trajectory
-// is a rotation about z (no z term in the u and w rows).
-void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeBPView> *out, bool *axial)
+// is a rotation about z (no z term in the u and w rows); out64 receives the
+// same rows in double precision.
+void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<ConeBPView> *out, bool *axial,
+              std::vector<ConeBPView64> *out64)
 {
     const double cu = 0.5 * (g->det_shape[1] - 1), cv = 0.5 * (g->det_shape[0] - 1);
     const double s[3] = {g->vol_spacing[2], g->vol_spacing[1], g->vol_spacing[0]};
@@ -245,6 +248,7 @@ void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
     for (int a = 0; a < 3; ++a)
         oc[a] = g->vol_origin[2 - a] + 0.5 * (g->vol_shape[2 - a] - 1) * (double)g->vol_spacing[2 - a];
     out->resize((size_t)g->n_proj);
+    out64->resize((size_t)g->n_proj);
     *axial = true;
     for (int k = 0; k < g->n_proj; ++k) {
         const double *m = &P[12 * (size_t)k];
@@ -255,10 +259,13 @@ void bp_views(const ph_geom3d *g, const std::vector<double> &P, std::vector<Cone
             r[2][t] = m[8 + t];
         }
         ConeBPView &v = (*out)[(size_t)k];
+        ConeBPView64 &v64 = (*out64)[(size_t)k];
         for (int row = 0; row < 3; ++row) {
             for (int a = 0; a < 3; ++a)
-                v.r[row][a] = (float)(r[row][a] * s[a]);
-            v.r[row][3] = (float)(r[row][0] * oc[0] + r[row][1] * oc[1] + r[row][2] * oc[2] + r[row][3]);
+                v64.r[row][a] = r[row][a] * s[a];
+            v64.r[row][3] = r[row][0] * oc[0] + r[row][1] * oc[1] + r[row][2] * oc[2] + r[row][3];
+            for (int a = 0; a < 4; ++a)
+                v.r[row][a] = (float)v64.r[row][a];
         }
         if (v.r[0][2] != 0.0f || v.r[2][2] != 0.0f)
             *axial = false;
@@ -547,14 +554,33 @@ int upload3d(const ph_geom3d *g, const float *mats, const std::vector<double> &P
     int st = PH_OK;
     if (for_bp) {
         std::vector<ConeBPView> v;
-        bp_views(g, P, &v, axial);
-        *views = cached(key, [&] { return as_bytes(v); }, &st);
+        std::vector<ConeBPView64> v64;
+        bp_views(g, P, &v, axial, &v64);
+        *views = cached(
+            key,
+            [&] {
+                // the FP64 rows follow the FP32 ones for the general (per-voxel) paths
+                std::vector<unsigned char> b = as_bytes(v);
+                if (!*axial) {
+                    const std::vector<unsigned char> b64 = as_bytes(v64);
+                    b.insert(b.end(), b64.begin(), b64.end());
+                }
+                return b;
+            },
+            &st);
     } else {
         std::vector<ConeFPView> v;
         fp_views(g, P, &v);
         *views = cached(key, [&] { return as_bytes(v); }, &st);
     }
     return st;
+}
+
+// The FP64 rows that follow the FP32 ones in a back-projector table of a
+// trajectory that is not a rotation about z; NULL for a circular one.
+const ConeBPView64 *views64_of(const void *views, bool axial, int n_proj)
+{
+    return axial ? nullptr : reinterpret_cast<const ConeBPView64 *>((const ConeBPView *)views + n_proj);
 }
 
 int prep3d(const ph_geom3d *g, const float *mats, bool for_bp, Geom3D *G, const void **views, bool *axial)
@@ -828,31 +854,31 @@ int ph_projection_matrices_3d(const ph_geom3d *g, float *mats)
     return PH_OK;
 }
 
-int ph_project_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, int dtype,
+int ph_project_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, ph_dtype dtype,
                      void *stream)
 {
     return project2d(g, false, rv, img, sino, batch, dtype, stream);
 }
 
-int ph_project_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, int dtype,
+int ph_project_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, ph_dtype dtype,
                      void *stream)
 {
     return project2d(g, true, rv, img, sino, batch, dtype, stream);
 }
 
-int ph_backproject_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+int ph_backproject_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                          void *stream)
 {
     return backproject2d(g, false, rv, sino, img, batch, dtype, stream);
 }
 
-int ph_backproject_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+int ph_backproject_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                          void *stream)
 {
     return backproject2d(g, true, rv, sino, img, batch, dtype, stream);
 }
 
-int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch, int dtype,
+int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch, ph_dtype dtype,
                       void *stream)
 {
     if (!vol || !proj)
@@ -872,7 +898,7 @@ int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, vo
         launch_project_cone(dtype, G, (const ConeFPView *)views, vol, proj, batch, (hipStream_t)stream));
 }
 
-int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch, int dtype,
+int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch, ph_dtype dtype,
                           void *stream)
 {
     if (!vol || !proj)
@@ -888,18 +914,18 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
     st = prep3d(g, mats, true, &G, &views, &axial);
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), proj, false,
-                                             vol, batch, (hipStream_t)stream));
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, views64_of(views, axial, g->n_proj),
+                                             axial, bp_segment(g), proj, false, vol, batch, (hipStream_t)stream));
 }
 
 int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
-                        const float *W_red, int batch, int dtype, void *stream)
+                        const float *W_red, int batch, ph_dtype dtype, void *stream)
 {
     return weight_filter2d(g, fan != 0, sino, out, K, M, W_red, batch, dtype, stream);
 }
 
 int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M, const float *W_red,
-                        const float *W, int batch, int dtype, void *stream)
+                        const float *W, int batch, ph_dtype dtype, void *stream)
 {
     if (!proj || !out)
         return PH_ERR_NULL;
@@ -937,20 +963,30 @@ size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch)
     return round_up((size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1] * sizeof(float));
 }
 
+size_t ph_fdk_workspace_bytes(const ph_geom3d *g, int M, int batch, ph_dtype dtype)
+{
+    if (check_dtype(dtype) != PH_OK || !g || g->det_shape[1] < 1)
+        return 0;
+    // M = 0: the default Ram-Lak length; otherwise a length some response K may have
+    if (M != 0 && !(is_pow2(M) && M >= 16 && M >= g->det_shape[1] && M <= 4096))
+        return 0;
+    return ph_workspace_bytes_3d(g, batch);
+}
+
 int ph_fbp_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
-                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     return fbp2d(g, false, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
 }
 
 int ph_fbp_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
-                 const float *W_red, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+                 const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     return fbp2d(g, true, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
 }
 
 int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
-                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, int dtype, void *stream)
+                  const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     if (!proj || !vol)
         return PH_ERR_NULL;
@@ -983,36 +1019,36 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
     st = to_status(launch_weight_filter(dtype, a, proj, q, (hipStream_t)stream));
     if (st != PH_OK)
         return st;
-    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), q, true, vol,
-                                             batch, (hipStream_t)stream));
+    return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, views64_of(views, axial, g->n_proj),
+                                             axial, bp_segment(g), q, true, vol, batch, (hipStream_t)stream));
 }
 
-int ph_project_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+int ph_project_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                              void *stream)
 {
     return adjoint2d(g, false, true, rv, sino, img, batch, dtype, stream);
 }
 
-int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, int dtype,
+int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                              void *stream)
 {
     return adjoint2d(g, true, true, rv, sino, img, batch, dtype, stream);
 }
 
 int ph_backproject_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
-                                 int dtype, void *stream)
+                                 ph_dtype dtype, void *stream)
 {
     return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
-                                 int dtype, void *stream)
+                                 ph_dtype dtype, void *stream)
 {
     return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
-                              int dtype, void *stream)
+                              ph_dtype dtype, void *stream)
 {
     if (!proj || !vol)
         return PH_ERR_NULL;
@@ -1039,7 +1075,7 @@ int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void 
 }
 
 static int bpT3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws, size_t ws_bytes,
-                 bool ws_call, int batch, int dtype, void *stream)
+                 bool ws_call, int batch, ph_dtype dtype, void *stream)
 {
     if (!proj || !vol)
         return PH_ERR_NULL;
@@ -1065,7 +1101,8 @@ static int bpT3d(const ph_geom3d *g, const float *mats, const void *vol, void *p
     if (st != PH_OK)
         return st;
     float *acc = via_ws ? (float *)ws : (float *)proj;
-    st = to_status(launch_backproject_adjoint_cone(dtype, G, (const ConeBPView *)views, axial, bp_segment(g), vol, acc,
+    st = to_status(launch_backproject_adjoint_cone(dtype, G, (const ConeBPView *)views,
+                                                   views64_of(views, axial, g->n_proj), axial, bp_segment(g), vol, acc,
                                                    batch, (hipStream_t)stream));
     if (st != PH_OK || !via_ws)
         return st;
@@ -1073,19 +1110,19 @@ static int bpT3d(const ph_geom3d *g, const float *mats, const void *vol, void *p
 }
 
 int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
-                                  int dtype, void *stream)
+                                  ph_dtype dtype, void *stream)
 {
     return bpT3d(g, mats, vol, proj, nullptr, 0, false, batch, dtype, stream);
 }
 
-size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, int dtype)
+size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, ph_dtype dtype)
 {
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1 || check_dtype(dtype) != PH_OK || dtype == PH_F32)
         return 0;
     return round_up((size_t)batch * g->n_proj * g->det_shape * sizeof(float));
 }
 
-size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, int dtype)
+size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, ph_dtype dtype)
 {
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1 || check_dtype(dtype) != PH_OK ||
         dtype == PH_F32)
@@ -1094,19 +1131,19 @@ size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, 
 }
 
 int ph_backproject_adjoint_ws_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
-                                    size_t ws_bytes, int batch, int dtype, void *stream)
+                                    size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
 }
 
 int ph_backproject_adjoint_ws_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
-                                    size_t ws_bytes, int batch, int dtype, void *stream)
+                                    size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
 }
 
 int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws,
-                                     size_t ws_bytes, int batch, int dtype, void *stream)
+                                     size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
     return bpT3d(g, mats, vol, proj, ws, ws_bytes, true, batch, dtype, stream);
 }
@@ -1366,3 +1403,4 @@ int ph_tv_iterate_cone3d(const ph_geom3d *g, const float *mats, const float *pro
 }
 
 }  // extern "C"
+

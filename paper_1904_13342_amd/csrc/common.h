@@ -65,6 +65,19 @@ struct ConeBPView {
     float r[3][4];
 };
 
+// The same rows in double precision, for trajectories that are not a rotation
+// about z.  There every voxel is projected on its own (no per-column
+// shortcut), and FP32 rows and positions would place it only to ~ulp(|u|)
+// ~ 3e-5 pixel on a detector a thousand pixels wide; the transpose of the
+// back-projector at high magnification (a voxel projecting onto several
+// pixels) is sensitive to exactly that.  Full-rate FP64 VALU on gfx950 makes
+// the FP64 projection cost about what the FP32 one does per instruction.
+// The library's cached back-projector table of such a trajectory holds
+// n_proj ConeBPView followed by n_proj ConeBPView64.
+struct ConeBPView64 {
+    double r[3][4];
+};
+
 // Per-view parameters of the cone forward projector (world mm, isocentre at
 // the origin): source s; the ray of centred pixel (jc, ic) has direction
 // d0 + jc*du + ic*dv (not normalised, pointing away from the source).
@@ -90,8 +103,11 @@ hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *vie
                                int batch, hipStream_t stream);
 // nz_seg: voxels per thread column segment (16 or 32), chosen by the host
 // so that a brick's detector footprint fits the LDS tile (64 x 128 pixels).
-hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
-                                   const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream);
+// views64: the FP64 rows of a trajectory that is not a rotation about z
+// (axial = false), NULL otherwise.
+hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64,
+                                   bool axial, int nz_seg, const void *proj, bool proj_is_f32, void *vol, int batch,
+                                   hipStream_t stream);
 
 // Exact transposes.  A^T: any storage type (gather, written once).  B^T:
 // FP32 in and out (scatter with float atomics into a zero-filled output).
@@ -102,8 +118,10 @@ hipError_t launch_project_adjoint_cone(int dtype, const Geom3D &g, const ConeFPV
                                        hipStream_t stream);
 hipError_t launch_backproject_adjoint_2d(int in_dtype, bool fan, const Geom2D &g, const float2 *views,
                                          const void *img, float *sino, int batch, hipStream_t stream);
-hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views, bool axial,
-                                           int nz_seg, const void *vol, float *proj, int batch, hipStream_t stream);
+// The output is zero-filled first.
+hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views,
+                                           const ConeBPView64 *views64, bool axial, int nz_seg, const void *vol,
+                                           float *proj, int batch, hipStream_t stream);
 // out[i] = in[i] rounded to the storage type (nearest even)
 hipError_t launch_cast_from_f32(int dtype, const float *in, void *out, size_t n, hipStream_t stream);
 // zero-fill kernel (used in place of a memset, which would not replay

@@ -16,7 +16,7 @@
 // For a circular trajectory about z (AXIAL: the matrices have no z term in
 // the u and w rows) the column coordinate, the depth w and the weight are
 // constant along a column, and only the row coordinate moves with z: one FMA
-// per voxel.  General matrices take the per-voxel path.
+// per voxel.  General matrices take the per-voxel path, projected in FP64.
 #include "device_util.h"
 
 namespace ph {
@@ -112,8 +112,52 @@ __device__ __forceinline__ float det_coord(float c, float centre)
     return c + centre;
 }
 
+// Projection of one voxel in a view of a general trajectory, in double
+// precision from the FP64 rows: the cell (j, i) of its bilinear footprint
+// relative to (u_lo, v_lo) (a staged tile's corner, or 0 for the detector
+// itself), the fractions within the cell and the distance weight
+// (SID/w)^2.  Shared by B and B^T, so the pair sees bitwise the same
+// positions.
+struct DetPoint {
+    int j, i;
+    float fu, fv, wt;
+};
+
+__device__ __forceinline__ DetPoint general_point(const ConeBPView64 &v, const Geom3D &g, float xc, float yc,
+                                                  float zc, int u_lo, int v_lo)
+{
+#pragma clang fp contract(off)
+    const double x = xc, y = yc, z = zc;
+    const double U = fma(v.r[0][0], x, fma(v.r[0][1], y, fma(v.r[0][2], z, v.r[0][3])));
+    const double V = fma(v.r[1][0], x, fma(v.r[1][1], y, fma(v.r[1][2], z, v.r[1][3])));
+    const double W = fma(v.r[2][0], x, fma(v.r[2][1], y, fma(v.r[2][2], z, v.r[2][3])));
+    const double rW = 1.0 / W;
+    const double su = fma(U, rW, (double)g.cu - (double)u_lo);
+    const double sv = fma(V, rW, (double)g.cv - (double)v_lo);
+    const double fsu = floor(su), fsv = floor(sv);
+    const double sw = (double)g.sid * rW;
+    DetPoint p;
+    p.j = (int)fsu;
+    p.i = (int)fsv;
+    p.fu = (float)(su - fsu);
+    p.fv = (float)(sv - fsv);
+    p.wt = (float)(sw * sw);
+    return p;
+}
+
+// bilinear fetch of cell (j, i) of a detector image, zero outside it
+template <typename TI>
+__device__ __forceinline__ float bilerp_cell(const TI *q, const Geom3D &g, int j, int i, float fu, float fv)
+{
+    const float p00 = det_pix(q, g.nu, g.nv, i, j), p01 = det_pix(q, g.nu, g.nv, i, j + 1);
+    const float p10 = det_pix(q, g.nu, g.nv, i + 1, j), p11 = det_pix(q, g.nu, g.nv, i + 1, j + 1);
+    const float a0 = fmaf(fu, p01 - p00, p00), a1 = fmaf(fu, p11 - p10, p10);
+    return fmaf(fv, a1 - a0, a0);
+}
+
 template <typename T, typename TI, int BP_NZ, bool AXIAL>
 __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                      const ConeBPView64 *__restrict__ views64,
                                                       const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
                                                       int nby, int nzb)
 {
@@ -201,23 +245,15 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
                         acc[z] = fmaf(wt, bilerp_global(qk, g, su, fmaf((float)z, dvz, sv0)), acc[z]);
             }
         } else {
+            const ConeBPView64 &v64 = views64[k];
 #pragma unroll
             for (int z = 0; z < BP_NZ; ++z) {
                 if (z < zcount) {
-                    const float zc = zc0 + (float)z;
-                    const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
-                    const float sw = g.sid * rW, wt = sw * sw;
-                    const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
-                    const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
-                    if (staged) {
-                        const float lu = su - (float)u_lo, lv = sv - (float)v_lo;
-                        const int iu = (int)lu, iv = (int)lv;
-                        acc[z] = fmaf(wt, bilerp_tile(tile + iv * BP_TS + iu, __builtin_amdgcn_fractf(lu),
-                                                      __builtin_amdgcn_fractf(lv)),
-                                      acc[z]);
-                    } else {
-                        acc[z] = fmaf(wt, bilerp_global(qk, g, su, sv), acc[z]);
-                    }
+                    const DetPoint d =
+                        general_point(v64, g, xc, yc, zc0 + (float)z, staged ? u_lo : 0, staged ? v_lo : 0);
+                    const float val = staged ? bilerp_tile(tile + d.i * BP_TS + d.j, d.fu, d.fv)
+                                             : bilerp_cell(qk, g, d.j, d.i, d.fu, d.fv);
+                    acc[z] = fmaf(d.wt, val, acc[z]);
                 }
             }
         }
@@ -269,6 +305,22 @@ __device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su
     const float fsu = floorf(su), fsv = floorf(sv);
     const int j = (int)fsu, i = (int)fsv;
     const float fu = su - fsu, fv = sv - fsv;
+    const float a = x * (1.0f - fv), b = x * fv;
+    const bool r0 = (unsigned)i < (unsigned)g.nv, r1 = (unsigned)(i + 1) < (unsigned)g.nv;
+    const bool c0 = (unsigned)j < (unsigned)g.nu, c1 = (unsigned)(j + 1) < (unsigned)g.nu;
+    if (r0 && c0)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j, a * (1.0f - fu));
+    if (r0 && c1)
+        unsafeAtomicAdd(q + (size_t)i * g.nu + j + 1, a * fu);
+    if (r1 && c0)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j, b * (1.0f - fu));
+    if (r1 && c1)
+        unsafeAtomicAdd(q + (size_t)(i + 1) * g.nu + j + 1, b * fu);
+}
+
+// splat into cell (j, i) of a detector image, skipping pixels outside it
+__device__ __forceinline__ void splat_cell(float *q, const Geom3D &g, int j, int i, float fu, float fv, float x)
+{
     const float a = x * (1.0f - fv), b = x * fv;
     const bool r0 = (unsigned)i < (unsigned)g.nv, r1 = (unsigned)(i + 1) < (unsigned)g.nv;
     const bool c0 = (unsigned)j < (unsigned)g.nu, c1 = (unsigned)(j + 1) < (unsigned)g.nu;
@@ -403,6 +455,7 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
 // General projection matrices: one thread per column segment, as in B.
 template <typename TI, int BP_NZ>
 __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBPView *__restrict__ views,
+                                                          const ConeBPView64 *__restrict__ views64,
                                                           const TI *__restrict__ vol, float *__restrict__ proj,
                                                           int nbx, int nby, int nzb)
 {
@@ -442,22 +495,16 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
         if (staged)
             __syncthreads();   // the previous tile has been flushed and cleared
         if (active) {
+            const ConeBPView64 &v64 = views64[k];
 #pragma unroll
             for (int z = 0; z < BP_NZ; ++z) {
                 if (z < zcount) {
-                    const float zc = zc0 + (float)z;
-                    const float rW = rcp_nr(dot4(v.r[2], xc, yc, zc));
-                    const float sw = g.sid * rW, wt = sw * sw;
-                    const float su = dot4(v.r[0], xc, yc, zc) * rW + g.cu;
-                    const float sv = dot4(v.r[1], xc, yc, zc) * rW + g.cv;
-                    if (staged) {
-                        const float lu = su - (float)fp.u_lo, lv = sv - (float)fp.v_lo;
-                        const int iu = (int)lu, iv = (int)lv;
-                        splat_tile(tile + iv * BPT_TS + iu, wt * val[z], __builtin_amdgcn_fractf(lu),
-                                   __builtin_amdgcn_fractf(lv), BPT_TS);
-                    } else {
-                        splat_global(qk, g, su, sv, wt * val[z]);
-                    }
+                    const DetPoint d = general_point(v64, g, xc, yc, zc0 + (float)z, staged ? fp.u_lo : 0,
+                                                     staged ? fp.v_lo : 0);
+                    if (staged)
+                        splat_tile(tile + d.i * BPT_TS + d.j, d.wt * val[z], d.fu, d.fv, BPT_TS);
+                    else
+                        splat_cell(qk, g, d.j, d.i, d.fu, d.fv, d.wt * val[z]);
                 }
             }
         }
@@ -469,49 +516,54 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
 }
 
 template <typename T, typename TI, int NZ>
-hipError_t bp_cone_nz(const Geom3D &g, const ConeBPView *views, bool axial, const void *proj, void *vol, int batch,
-                      hipStream_t s)
+hipError_t bp_cone_nz(const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64, bool axial,
+                      const void *proj, void *vol, int batch, hipStream_t s)
 {
     const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
     const unsigned blocks = (unsigned)(nbx * nby * nzb * batch);
     if (axial)
         hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, true>), dim3(blocks), dim3(256), 0, s, g, views,
-                           (const TI *)proj, (T *)vol, nbx, nby, nzb);
+                           (const ConeBPView64 *)nullptr, (const TI *)proj, (T *)vol, nbx, nby, nzb);
     else
-        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, false>), dim3(blocks), dim3(256), 0, s, g, views,
+        hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, false>), dim3(blocks), dim3(256), 0, s, g, views, views64,
                            (const TI *)proj, (T *)vol, nbx, nby, nzb);
     return hipGetLastError();
 }
 
 template <typename T, typename TI>
-hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg, const void *proj, void *vol,
-                   int batch, hipStream_t s)
+hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64, bool axial, int nz_seg,
+                   const void *proj, void *vol, int batch, hipStream_t s)
 {
+    if (!axial && !views64)
+        return hipErrorInvalidValue;
     if (nz_seg >= 32)
-        return bp_cone_nz<T, TI, 32>(g, views, axial, proj, vol, batch, s);
-    return bp_cone_nz<T, TI, 16>(g, views, axial, proj, vol, batch, s);
+        return bp_cone_nz<T, TI, 32>(g, views, views64, axial, proj, vol, batch, s);
+    return bp_cone_nz<T, TI, 16>(g, views, views64, axial, proj, vol, batch, s);
 }
 
 }  // namespace
 
-hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg,
-                                   const void *proj, bool proj_is_f32, void *vol, int batch, hipStream_t stream)
+hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64,
+                                   bool axial, int nz_seg, const void *proj, bool proj_is_f32, void *vol, int batch,
+                                   hipStream_t stream)
 {
     switch (dtype) {
-    case 0: return bp_cone<float, float>(g, views, axial, nz_seg, proj, vol, batch, stream);
+    case 0: return bp_cone<float, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
     case 1:
-        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, axial, nz_seg, proj, vol, batch, stream)
-                           : bp_cone<f16_t, f16_t>(g, views, axial, nz_seg, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream)
+                           : bp_cone<f16_t, f16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
     default:
-        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, axial, nz_seg, proj, vol, batch, stream)
-                           : bp_cone<bf16_t, bf16_t>(g, views, axial, nz_seg, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream)
+                           : bp_cone<bf16_t, bf16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
     }
 }
 
 template <typename TI>
-hipError_t bpT_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz_seg, const void *vol, float *proj,
-                    int batch, hipStream_t stream)
+hipError_t bpT_cone(const Geom3D &g, const ConeBPView *views, const ConeBPView64 *v64, bool axial, int nz_seg,
+                    const void *vol, float *proj, int batch, hipStream_t stream)
 {
+    if (!axial && !v64)
+        return hipErrorInvalidValue;
     const int NZ = nz_seg >= 32 ? 32 : 16;
     const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
     const dim3 grid((unsigned)(nbx * nby * nzb * batch));
@@ -521,29 +573,30 @@ hipError_t bpT_cone(const Geom3D &g, const ConeBPView *views, bool axial, int nz
             hipLaunchKernelGGL((bpT_axial_kernel<TI, 32>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
                                nzb);
         else
-            hipLaunchKernelGGL((bpT_general_kernel<TI, 32>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
-                               nzb);
+            hipLaunchKernelGGL((bpT_general_kernel<TI, 32>), grid, dim3(256), 0, stream, g, views, v64, v, proj, nbx,
+                               nby, nzb);
     } else {
         if (axial)
             hipLaunchKernelGGL((bpT_axial_kernel<TI, 16>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
                                nzb);
         else
-            hipLaunchKernelGGL((bpT_general_kernel<TI, 16>), grid, dim3(256), 0, stream, g, views, v, proj, nbx, nby,
-                               nzb);
+            hipLaunchKernelGGL((bpT_general_kernel<TI, 16>), grid, dim3(256), 0, stream, g, views, v64, v, proj, nbx,
+                               nby, nzb);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views, bool axial,
-                                           int nz_seg, const void *vol, float *proj, int batch, hipStream_t stream)
+hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const ConeBPView *views,
+                                           const ConeBPView64 *views64, bool axial, int nz_seg, const void *vol,
+                                           float *proj, int batch, hipStream_t stream)
 {
     hipError_t e = fill_zero(proj, (size_t)batch * g.n_proj * g.nv * g.nu, stream);
     if (e != hipSuccess)
         return e;
     switch (in_dtype) {
-    case 0: return bpT_cone<float>(g, views, axial, nz_seg, vol, proj, batch, stream);
-    case 1: return bpT_cone<f16_t>(g, views, axial, nz_seg, vol, proj, batch, stream);
-    default: return bpT_cone<bf16_t>(g, views, axial, nz_seg, vol, proj, batch, stream);
+    case 0: return bpT_cone<float>(g, views, views64, axial, nz_seg, vol, proj, batch, stream);
+    case 1: return bpT_cone<f16_t>(g, views, views64, axial, nz_seg, vol, proj, batch, stream);
+    default: return bpT_cone<bf16_t>(g, views, views64, axial, nz_seg, vol, proj, batch, stream);
     }
 }
 

@@ -449,6 +449,10 @@ def workspace_bytes_3d(g, batch=1):
     return int(lib().ph_workspace_bytes_3d(ctypes.byref(g), int(batch)))
 
 
+def fdk_workspace_bytes(g, M=0, batch=1, dtype=torch.float32):
+    return int(lib().ph_fdk_workspace_bytes(ctypes.byref(g), int(M), int(batch), _DTYPES[dtype]))
+
+
 def _fbp2d(fn, g, ray_vecs, sino, K, M, W_red, out, ws):
     batch = _dev(sino, "sino", _sino_tail(g))
     t = _traj(g, ray_vecs)
@@ -483,7 +487,7 @@ def fdk_cone3d(g, mats, proj, K=None, M=None, W_red=None, W=None, out=None, ws=N
     shape = (tuple(proj.shape[:1]) if proj.dim() == 4 else ()) + _vol_tail(g)
     if out is None:
         out = torch.empty(shape, dtype=proj.dtype, device=proj.device)
-    nbytes = workspace_bytes_3d(g, batch)
+    nbytes = fdk_workspace_bytes(g, M, batch, proj.dtype)
     if ws is None:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=proj.device)
     status = lib().ph_fdk_cone3d(ctypes.byref(g), _fptr(t), ctypes.c_void_p(proj.data_ptr()),
@@ -504,7 +508,8 @@ __all__ = [
     "project_fan2d", "project_cone3d", "backproject_par2d", "backproject_fan2d", "backproject_cone3d",
     "project_adjoint_par2d", "project_adjoint_fan2d", "project_adjoint_cone3d", "backproject_adjoint_par2d",
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
-    "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fbp_par2d",
+    "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fdk_workspace_bytes",
+    "fbp_par2d",
     "fbp_fan2d", "fdk_cone3d", "filter_response", "filter_response_equiangular", "tv", "tv_workspace_bytes",
     "tv_iterate", "mse_grad",
     "corrector_grad_3d", "corrector_grad_2d", "adam_step", "version",

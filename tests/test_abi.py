@@ -168,8 +168,14 @@ def test_rejects_bad_filter_length_and_workspace(ph, L):
     g = _good3(ph)
     mats = ph.projection_matrices_3d(g)
     fp = mats.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-    ws_need = L.ph_workspace_bytes_3d(ctypes.byref(g), 1)
+    ws_need = L.ph_fdk_workspace_bytes(ctypes.byref(g), 0, 1, 0)
     assert ws_need >= 360 * 48 * 48 * 4
+    # the FP32 filtered projections whatever the filter length and storage type
+    for M, dt in ((0, 0), (64, 1), (4096, 2)):
+        assert L.ph_fdk_workspace_bytes(ctypes.byref(g), M, 1, dt) == ws_need
+    assert L.ph_fdk_workspace_bytes(ctypes.byref(g), 0, 3, 0) == L.ph_workspace_bytes_3d(ctypes.byref(g), 3)
+    for M, dt, b in ((100, 0, 1), (32, 0, 1), (8192, 0, 1), (0, 3, 1), (0, 0, 0)):
+        assert L.ph_fdk_workspace_bytes(ctypes.byref(g), M, b, dt) == 0, (M, dt, b)
     # too-small workspace
     assert L.ph_fdk_cone3d(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, FAKE, ws_need - 1, 1, 0, None) == -5
     assert L.ph_fdk_cone3d(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, None, ws_need, 1, 0, None) == -5
