@@ -10,6 +10,17 @@ import torch
 import synth
 
 FP32_TOL = 1e-5   # rel-L2 bound of FP32 kernels against the FP64 oracle
+# Bound on every single element, as a fraction of the largest reference
+# magnitude: FP32 sample positions carry ~3e-5 voxel of rounding (coordinates
+# up to a few hundred), which moves a sample across a unit jump of the
+# phantom by at most that much, so one element of a line integral or a
+# back-projected sum may differ by a few 1e-5 of the largest value; 1e-4
+# leaves a factor of three.  A seam error (a tile, slab or brick edge handled
+# wrongly) shows up here even where the rel-L2 over a large array hides it.
+ELEM_TOL = 1e-4
+# Storage rounding of one element (nearest even): 2^-11 (FP16) and 2^-8
+# (BF16) of the element, doubled.
+ELEM_TOL_HALF = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}
 
 
 def device():
@@ -27,6 +38,28 @@ def rel_l2(x, ref):
     x = np.asarray(x, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+def max_rel(x, ref):
+    """max |x - ref| / max |ref| over all elements."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def check(x, ref, what="", tol=FP32_TOL, elem=ELEM_TOL):
+    """Assert rel-L2(x, ref) < tol and every element within elem * max|ref|;
+    prints both figures."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert x.shape == ref.shape, (what, x.shape, ref.shape)
+    assert np.abs(ref).max() > 0, what
+    assert np.all(np.isfinite(x)), what
+    err, mx = rel_l2(x, ref), max_rel(x, ref)
+    say(f"  {what} rel-L2 {err:.2e}, max elem {mx:.2e}")
+    assert err < tol, (what, err, tol)
+    assert mx <= elem, (what, mx, elem)
+    return err
 
 
 def to_dev(a, dtype=torch.float32):

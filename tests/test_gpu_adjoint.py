@@ -12,7 +12,7 @@ import torch
 
 import gpu_common as gc
 import synth
-from gpu_common import FP32_TOL, as_f32, rel_l2, say, to_dev, to_np
+from gpu_common import FP32_TOL, check, as_f32, rel_l2, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -55,9 +55,7 @@ def test_project_adjoint_parity(ph, ora, name):
     g, traj, _, fT, _, _ = _ops(ph, spec)
     p = as_f32(ora.project(spec, gc.phantom(spec)))       # realistic projection data
     out = fT(g, traj, to_dev(p))
-    err = rel_l2(to_np(out), ora.project_adjoint(spec, p))
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ora.project_adjoint(spec, p), "")
 
 
 @pytest.mark.parametrize("name", list(SPECS))
@@ -67,9 +65,7 @@ def test_backproject_adjoint_parity(ph, ora, name):
     g, traj, _, _, _, bT = _ops(ph, spec)
     f = gc.phantom(spec)
     out = bT(g, traj, to_dev(f))
-    err = rel_l2(to_np(out), ora.backproject_adjoint(spec, f))
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ora.backproject_adjoint(spec, f), "")
 
 
 def test_backproject_adjoint_plain_entry_rejects_half(ph):

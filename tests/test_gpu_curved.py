@@ -10,7 +10,7 @@ import torch
 
 import gpu_common as gc
 import synth
-from gpu_common import FP32_TOL, as_f32, rel_l2, say, to_dev, to_np
+from gpu_common import FP32_TOL, check, as_f32, rel_l2, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +49,7 @@ def test_project(ph, ora, name):
     say(f"[curved project] {name}")
     f = gc.phantom(spec)
     out = ph.project_fan2d(g, rv, to_dev(f))
-    err = rel_l2(to_np(out), ora.project(spec, f))
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ora.project(spec, f), "")
 
 
 @pytest.mark.parametrize("name", list(SPECS))
@@ -61,9 +59,7 @@ def test_backproject(ph, ora, name):
     f = gc.phantom(spec)
     q = as_f32(ora.filter_projections(spec, ora.weight(spec, ora.project(spec, f))).reshape(spec.n_proj, -1))
     out = ph.backproject_fan2d(g, rv, to_dev(q))
-    err = rel_l2(to_np(out), ora.backproject(spec, q))
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ora.backproject(spec, q), "")
 
 
 @pytest.mark.parametrize("name", list(SPECS))
@@ -75,9 +71,7 @@ def test_weight_filter(ph, ora, name):
     p = as_f32(ora.project(spec, gc.phantom(spec)))
     out = ph.weight_filter_2d(g, to_dev(p), True)
     ref = ora.filter_projections(spec, ora.weight(spec, p)).reshape(spec.n_proj, -1)
-    err = rel_l2(to_np(out), ref)
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ref, "")
 
 
 @pytest.mark.parametrize("name", list(SPECS))
@@ -86,9 +80,7 @@ def test_fbp(ph, ora, name):
     say(f"[curved fbp] {name}")
     p = as_f32(ora.project(spec, gc.phantom(spec)))
     out = ph.fbp_fan2d(g, rv, to_dev(p))
-    err = rel_l2(to_np(out), ora.fbp(spec, p))
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ora.fbp(spec, p), "")
 
 
 @pytest.mark.parametrize("name", ["curved_ragged", "curved_wide"])
@@ -99,12 +91,8 @@ def test_transposes(ph, ora, name):
     # and its projections
     f = gc.phantom(spec)
     p = as_f32(ora.project(spec, f))
-    err = rel_l2(to_np(ph.project_adjoint_fan2d(g, rv, to_dev(p))), ora.project_adjoint(spec, p))
-    say(f"  A^T rel-L2 {err:.2e}")
-    assert err < FP32_TOL
-    err = rel_l2(to_np(ph.backproject_adjoint_fan2d(g, rv, to_dev(f))), ora.backproject_adjoint(spec, f))
-    say(f"  B^T rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(ph.project_adjoint_fan2d(g, rv, to_dev(p))), ora.project_adjoint(spec, p), "A^T")
+    check(to_np(ph.backproject_adjoint_fan2d(g, rv, to_dev(f))), ora.backproject_adjoint(spec, f), "B^T")
     # the GPU pairs are transposes of each other on signed noise (FP64 inner
     # products of the FP32 outputs)
     y = as_f32(synth.random_array((spec.n_proj, spec.det_shape[0]), 3))
@@ -124,9 +112,9 @@ def test_half_storage(ph, ora):
     f = gc.phantom(spec)
     fh = torch.tensor(f, dtype=torch.float16)
     out = ph.project_fan2d(g, rv, fh.cuda())
-    err = rel_l2(to_np(out), ora.project(spec, fh.double().numpy()))
-    say(f"[curved f16 project] rel-L2 {err:.2e}")
-    assert out.dtype == torch.float16 and err < 2e-3
+    assert out.dtype == torch.float16
+    check(to_np(out), ora.project(spec, fh.double().numpy()), "[curved f16 project]", tol=2e-3,
+          elem=gc.ELEM_TOL_HALF["f16"])
 
 
 def test_fbp_of_disk(ph, ora):

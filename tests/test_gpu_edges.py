@@ -12,7 +12,7 @@ import torch
 
 import gpu_common as gc
 import synth
-from gpu_common import FP32_TOL, as_f32, rel_l2, say, to_dev, to_np
+from gpu_common import FP32_TOL, check, as_f32, rel_l2, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +57,7 @@ def _all_ops(ph, ora, spec, seed):
             say(f"  {name}: reference is zero, max |gpu| {err:.2e}")
             assert err == 0.0
         else:
-            err = rel_l2(to_np(gpu), ref)
-            say(f"  {name}: rel-L2 {err:.2e}")
-            assert err < FP32_TOL, name
+            check(to_np(gpu), ref, f"{name}")
 
 
 CASES = {
@@ -98,12 +96,8 @@ def test_longest_filter(ph, ora):
     p = as_f32(synth.random_array((spec.n_proj, 2048), 5))
     out = ph.weight_filter_2d(g, to_dev(p), fan=False)
     ref = ora.filter_projections(spec, ora.weight(spec, p)).reshape(spec.n_proj, 2048)
-    err = rel_l2(to_np(out), ref)
-    say(f"[edge] Ram-Lak at M=4096: rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ref, "[edge] Ram-Lak at M=4096")
     K = as_f32(ora.ramp_response(4096, ora.tau(spec)) + 0.01 * synth.random_array((4096,), 6))
     out = ph.weight_filter_2d(g, to_dev(p), fan=False, K=to_dev(K))
     ref = ora.filter_projections(spec, ora.weight(spec, p), K=K).reshape(spec.n_proj, 2048)
-    err = rel_l2(to_np(out), ref)
-    say(f"[edge] learned K at M=4096: rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(to_np(out), ref, "[edge] learned K at M=4096")

@@ -20,7 +20,7 @@ import torch
 
 import gpu_common as gc
 import synth
-from gpu_common import FP32_TOL, as_f32, rel_l2, say, to_dev, to_np
+from gpu_common import FP32_TOL, check, as_f32, rel_l2, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -75,9 +75,7 @@ def test_filter_wave_cone(ph, ora, name):
     for b in range(batch):
         q = ora.weight(spec, p[b], W_red=W_red, W=W)
         ref = ora.filter_projections(spec, q, K=K).reshape(n_proj, nv, nu)
-        err = rel_l2(out[b], ref)
-        say(f"  batch {b}: rel-L2 {err:.2e}")
-        assert err < FP32_TOL
+        check(out[b], ref, f"batch {b}")
 
 
 @pytest.mark.parametrize("M", [1024, 2048])
@@ -93,9 +91,7 @@ def test_filter_wave_half_storage(ph, ora, dtype, M):
     K = as_f32(np.abs(synth.random_array((M,), 19)))
     out = to_np(ph.weight_filter_3d(g, p.to(gc.device()).contiguous(), K=to_dev(K)))
     ref = ora.filter_projections(spec, ora.weight(spec, stored), K=K).reshape(stored.shape)
-    err = rel_l2(out, ref)
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(out, ref, "")
 
 
 @pytest.mark.parametrize("M", [1024, 2048])
@@ -111,6 +107,4 @@ def test_filter_wave_arc_detector_learned(ph, ora, M):
     W_red = as_f32(synth.random_array((spec.n_proj, nu), 18, dist="uniform", low=0.5, high=1.5))
     out = to_np(ph.weight_filter_2d(g, to_dev(p), True, K=to_dev(K), W_red=to_dev(W_red)))
     ref = ora.filter_projections(spec, ora.weight(spec, p, W_red=W_red), K=K).reshape(p.shape)
-    err = rel_l2(out, ref)
-    say(f"  rel-L2 {err:.2e}")
-    assert err < FP32_TOL
+    check(out, ref, "")

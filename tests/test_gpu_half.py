@@ -15,12 +15,20 @@ import torch
 
 import gpu_common as gc
 import synth
-from gpu_common import as_f32, rel_l2, say, to_dev, to_np
+from gpu_common import ELEM_TOL_HALF, as_f32, check, rel_l2, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
 BOUND = {torch.float16: 2e-3, torch.bfloat16: 1e-2}
 DTYPES = [torch.float16, torch.bfloat16]
+
+
+def hcheck(out, ref, dtype, what):
+    """rel-L2 within the storage type's bound and every element within two
+    of its rounding steps of the largest value."""
+    assert out.dtype == dtype, (what, out.dtype)
+    return check(to_np(out), ref, what, tol=BOUND[dtype],
+                 elem=ELEM_TOL_HALF["f16" if dtype == torch.float16 else "bf16"])
 
 
 @pytest.fixture(scope="module")
@@ -49,11 +57,8 @@ def test_project_cone_half(ph, ora, dtype):
     g = ph.from_spec(spec)
     out = ph.project_cone3d(g, ph.projection_matrices_3d(g), to_dev(fq, dtype))
     assert out.dtype == dtype
-    ref = ora.project(spec, fq)
-    err = rel_l2(to_np(out), ref)
-    e2e = rel_l2(to_np(out), ora.project(spec, f))
-    say(f"[project_cone {dtype}] vs FP64 on stored input {err:.2e}; end to end {e2e:.2e}")
-    assert err < BOUND[dtype]
+    hcheck(out, ora.project(spec, fq), dtype, f"[project_cone {dtype}] vs FP64 on stored input")
+    say(f"  end to end {rel_l2(to_np(out), ora.project(spec, f)):.2e}")
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
@@ -66,15 +71,11 @@ def test_backproject_and_fdk_cone_half(ph, ora, dtype):
     q = as_f32(ora.filter_projections(spec, ora.weight(spec, p)))
     qq = quantise(q, dtype)
     out = ph.backproject_cone3d(g, mats, to_dev(qq, dtype))
-    err = rel_l2(to_np(out), ora.backproject(spec, qq))
-    e2e = rel_l2(to_np(out), ora.backproject(spec, q))
-    say(f"[backproject_cone {dtype}] {err:.2e}; end to end {e2e:.2e}")
-    assert out.dtype == dtype and err < BOUND[dtype]
+    hcheck(out, ora.backproject(spec, qq), dtype, f"[backproject_cone {dtype}]")
+    say(f"  end to end {rel_l2(to_np(out), ora.backproject(spec, q)):.2e}")
     rec = ph.fdk_cone3d(g, mats, to_dev(pq, dtype))
-    err = rel_l2(to_np(rec), ora.fbp(spec, pq))
-    e2e = rel_l2(to_np(rec), ora.fbp(spec, p))
-    say(f"[fdk_cone {dtype}] {err:.2e}; end to end {e2e:.2e}")
-    assert rec.dtype == dtype and err < BOUND[dtype]
+    hcheck(rec, ora.fbp(spec, pq), dtype, f"[fdk_cone {dtype}]")
+    say(f"  end to end {rel_l2(to_np(rec), ora.fbp(spec, p)):.2e}")
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
@@ -85,15 +86,11 @@ def test_fan2d_half(ph, ora, dtype):
     g = ph.from_spec(spec)
     rv = ph.ray_vectors_2d(g)
     sino = ph.project_fan2d(g, rv, to_dev(fq, dtype))
-    err = rel_l2(to_np(sino), ora.project(spec, fq))
-    say(f"[project_fan2d {dtype}] {err:.2e}")
-    assert sino.dtype == dtype and err < BOUND[dtype]
+    hcheck(sino, ora.project(spec, fq), dtype, f"[project_fan2d {dtype}]")
     sq = to_np(sino)
     rec = ph.fbp_fan2d(g, rv, sino)
-    err = rel_l2(to_np(rec), ora.fbp(spec, sq))
-    e2e = rel_l2(to_np(rec), ora.fbp(spec, ora.project(spec, f)))
-    say(f"[fbp_fan2d {dtype}] {err:.2e}; end to end {e2e:.2e}")
-    assert rec.dtype == dtype and err < BOUND[dtype]
+    hcheck(rec, ora.fbp(spec, sq), dtype, f"[fbp_fan2d {dtype}]")
+    say(f"  end to end {rel_l2(to_np(rec), ora.fbp(spec, ora.project(spec, f))):.2e}")
 
 
 def test_half_rounding_is_nearest_even(ph):
@@ -136,10 +133,6 @@ def test_adjoints_half(ph, ora, kind, dtype):
     p = as_f32(ora.project(spec, f))
     pq, fq = quantise(p, dtype), quantise(f, dtype)
     out = aT(g, traj, to_dev(pq, dtype))
-    err = rel_l2(to_np(out), ora.project_adjoint(spec, pq))
-    say(f"[project_adjoint {kind} {dtype}] {err:.2e}")
-    assert out.dtype == dtype and err < BOUND[dtype]
+    hcheck(out, ora.project_adjoint(spec, pq), dtype, f"[project_adjoint {kind} {dtype}]")
     out = bT(g, traj, to_dev(fq, dtype))
-    err = rel_l2(to_np(out), ora.backproject_adjoint(spec, fq))
-    say(f"[backproject_adjoint {kind} {dtype}] {err:.2e}")
-    assert out.dtype == dtype and err < BOUND[dtype]
+    hcheck(out, ora.backproject_adjoint(spec, fq), dtype, f"[backproject_adjoint {kind} {dtype}]")
