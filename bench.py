@@ -76,9 +76,12 @@ def parse():
     ap.add_argument("--config", default="cone3d_512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--workload", choices=("fdk", "corrector", "tv", "filter2d", "fan2d", "precision", "copyref"),
+    ap.add_argument("--workload", choices=("fdk", "adjoint", "corrector", "tv", "filter2d", "fan2d", "precision",
+                                           "copyref"),
                     default="fdk",
-                    help="fdk: the projector / FDK hot path (default); corrector: the learned-corrector training run; "
+                    help="fdk: the projector / FDK hot path (default); adjoint: the 512^3 operators as differentiable "
+                         "layers, forward and matched backward (A, A^T, B, B^T); "
+                         "corrector: the learned-corrector training run; "
                          "tv: sparse-view TV-regularised iterative reconstruction; "
                          "filter2d: learning the 2D reconstruction filter alone from the ramp; "
                          "precision: FP16 / BF16 storage against FP32 at 512^3 (RMSE and speed); "
@@ -543,12 +546,110 @@ def precision_main(args):
     print(json.dumps(line), flush=True)
 
 
+def adjoint_main(args):
+    """The 512^3 operators as differentiable layers with the matched pairing:
+    one step is a forward projection and its backward pass (A^T of the
+    incoming gradient) plus a back-projection and its backward pass (B^T),
+    driven through torch.autograd.  Each kernel is also timed on its own with
+    HIP events over the same launches, and reported against the VALU model
+    of the operator it transposes (A^T visits the forward projector's
+    samples, B^T the back-projector's voxel-view updates)."""
+    import numpy as np
+    import torch
+
+    import paper_1904_13342_amd as ph
+    import synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.config(args.config)
+    g = ph.from_spec(spec)
+    mats = ph.projection_matrices_3d(g)
+    prm = synth.random_ellipsoids(spec.seed, spec.n_figures, spec.vol_shape, spec.vol_spacing)
+    vol = synth.rasterize_ellipsoids(prm, spec.vol_shape, spec.vol_spacing, sub=1, device=dev,
+                                     dtype=torch.float32).contiguous()
+    gen = torch.Generator(device=dev).manual_seed(5)
+    w_proj = torch.randn((spec.n_proj,) + tuple(spec.det_shape), device=dev, generator=gen)   # dL/dp
+    w_vol = torch.randn(tuple(spec.vol_shape), device=dev, generator=gen)                     # dL/dx
+    q = ph.project_cone3d(g, mats, vol).requires_grad_(True)
+    x = vol.clone().requires_grad_(True)
+
+    def step():
+        x.grad = None
+        q.grad = None
+        p = ph.autograd.project(x, g, mats)
+        p.backward(w_proj)                 # x.grad = A^T w_proj
+        r = ph.autograd.backproject(q, g, mats)
+        r.backward(w_vol)                  # q.grad = B^T w_vol
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # each kernel alone, into preallocated outputs
+    out_p = torch.empty_like(w_proj)
+    out_v = torch.empty_like(w_vol)
+    calls = {"fp_cone": lambda: ph.project_cone3d(g, mats, vol, out=out_p),
+             "fpT_cone": lambda: ph.project_adjoint_cone3d(g, mats, w_proj, out=out_v),
+             "bp_cone": lambda: ph.backproject_cone3d(g, mats, q.detach(), out=out_v),
+             "bpT_cone": lambda: ph.backproject_adjoint_cone3d(g, mats, w_vol, out=out_p)}
+    ms = {}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        for k in range(args.steps):
+            ev[2 * k].record()
+            fn()
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        ms[name] = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps)]))
+    nz, ny, nx = spec.vol_shape
+    updates = nx * ny * nz * spec.n_proj
+    samples = count_samples(spec, dev)
+    kernels = {}
+    for name, units, ops, uname in (("fp_cone", samples, OPS_PER_SAMPLE, "ray samples"),
+                                    ("fpT_cone", samples, OPS_PER_SAMPLE, "ray samples (transposed)"),
+                                    ("bp_cone", updates, OPS_PER_UPDATE, "voxel-view updates"),
+                                    ("bpT_cone", updates, OPS_PER_UPDATE, "voxel-view updates (transposed)")):
+        ach = ops * units / (ms[name] * 1e-3) / 1e12
+        kernels[name] = {"bound": "alu", "ms": ms[name], "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                         "frac": ach / PEAK_VALU_TOPS, "units_per_launch": units, "unit_name": uname,
+                         "ops_per_unit": ops, "traffic": measured_traffic(name)}
+    dom_name = max(("fpT_cone", "bpT_cone"), key=lambda n: kernels[n]["ms"])
+    dom = kernels[dom_name]
+    line = {
+        "metric": "matched adjoint throughput at 512^3: A^T Gsamples/s and B^T GUPS (autograd backward)",
+        "value": samples / (ms["fpT_cone"] * 1e-3) / 1e9, "unit": "Gsamples/s (A^T)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: 12 seeded random ellipsoids and seeded Gaussian gradients, resident in HBM",
+        "config": {"workload": f"cone3d {nx}x{ny}x{nz} at {spec.vol_spacing[0]} mm, {spec.n_proj} views, "
+                               f"{spec.det_shape[1]}x{spec.det_shape[0]} detector at {spec.det_spacing[0]} mm",
+                   "step": "autograd: A forward + A^T backward, B forward + B^T backward"},
+        "fpT_gsamples_per_s": samples / (ms["fpT_cone"] * 1e-3) / 1e9,
+        "bpT_gups": updates / (ms["bpT_cone"] * 1e-3) / 1e9,
+        "fpT_over_fp": ms["fpT_cone"] / ms["fp_cone"], "bpT_over_bp": ms["bpT_cone"] / ms["bp_cone"],
+        "roofline": {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],
+                     "unit": dom["unit"], "frac": dom["frac"], "traffic": dom["traffic"]},
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): each GPU would run this same path "
               "on its own share of the views (projections) or z-slabs (volume).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "adjoint":
+        adjoint_main(args)
+        return
     if args.workload == "corrector":
         corrector_main(args)
         return

@@ -6,11 +6,9 @@
 // by gather and without atomics: voxel j receives
 //     step * sum_r g_r * sum_k Lambda(X_rk - j),
 // Lambda the tensor-product hat function, X_rk the same FP32 sample positions
-// the forward projector uses.  A thread owns a voxel (2D) or a column segment
-// (3D) and walks, per view, the rays that cross its support (j - 1, j + 1)^d.
-// In 3D the rays crossing a brick's support are set up once per view into an
-// LDS table shared by the block, and every thread accumulates its segment in
-// its own LDS slots.
+// the forward projector uses.  In 2D a thread owns a pixel and walks, per
+// view, the rays that cross its support (j - 1, j + 1)^2.  In 3D a workgroup
+// owns a brick and its rays splat into an LDS accumulator (below).
 //
 // B^T in 2D, the transpose of the voxel-driven distance-weighted
 // back-projector, scatters each pixel's value times dbeta * weight into the
@@ -92,138 +90,126 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
 }
 
 // --------------------------------------------------------------- A^T, 3D
+//
+// A workgroup owns a 16 x 16 x 16 brick of voxels and accumulates its
+// transpose in LDS over every view, in FP64, with a one-voxel halo on each
+// side (18^3 cells): a sample whose trilinear support touches the brick adds
+// its eight corner weights there, and corners in the halo belong to the
+// neighbouring bricks, which see the same sample, so they are dropped.  Per
+// view, the rays that can reach the brick's support are the detector pixels
+// in the support box's footprint (its 8 corners projected by eight lanes and
+// reduced with DPP); each lane takes one ray, sets it up exactly as the
+// forward projector does (FP64 set-up, the same biased FP32 sample positions,
+// so the pair is transposed sample for sample), clips it to the support box
+// and walks its samples there once, splatting each with eight LDS FP64
+// atomic adds at fixed offsets from one cell address.  No barrier is needed
+// between views: the accumulator only ever receives atomic adds.  The brick
+// is written once at the end, so the output needs no clearing and no global
+// atomics.
 
-constexpr int AT_NZ = 8;          // voxels per column segment
-constexpr int AT_RAYS = 1024;     // rays per view held in the block's LDS table
+constexpr int AT_B = 16;                 // brick edge (voxels)
+constexpr int AT_H = AT_B + 2;           // accumulator edge with the halo
+constexpr int AT_CELLS = AT_H * AT_H * AT_H;
 
 template <typename T, typename TI>
 __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPView *__restrict__ fviews,
                                                        const ConeBPView *__restrict__ bviews,
                                                        const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
-                                                       int nby, int nzb)
+                                                       int nby, int nbz)
 {
-    __shared__ float rtab[7][AT_RAYS];        // X0 Y0 Z0 eX eY eZ, step * g
-    __shared__ float accl[AT_NZ][256];        // per-thread segment accumulators
+    __shared__ double acc[AT_CELLS];
     const int tid = threadIdx.x;
     const int bxi = (int)(blockIdx.x % (unsigned)nbx), byi = (int)((blockIdx.x / (unsigned)nbx) % (unsigned)nby);
     const int bzb = (int)(blockIdx.x / (unsigned)(nbx * nby));
-    const int zb = bzb % nzb, b = bzb / nzb;
-    const int ix = bxi * 16 + (tid & 15), iy = byi * 16 + (tid >> 4);
-    const int z0 = zb * AT_NZ;
-    const bool active = ix < g.nx && iy < g.ny;
-    const float fx = (float)ix, fy = (float)iy;
-#pragma unroll
-    for (int z = 0; z < AT_NZ; ++z)
-        accl[z][tid] = 0.0f;
+    const int bzi = bzb % nbz, b = bzb / nbz;
+    const int x0 = bxi * AT_B, y0 = byi * AT_B, z0 = bzi * AT_B;
+    for (int n = tid; n < AT_CELLS; n += 256)
+        acc[n] = 0.0;
+    __syncthreads();
 
     const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
-    // support boxes in centred voxel indices: the brick's (for the table) and
-    // this column segment's (for its own loop)
+    // support box of the brick's voxels, (x0 - 1, min(x0 + B, N)) per axis:
+    // inside the grid's support (-1, N), which the host has checked lies in
+    // front of every source
+    const int xe = min(x0 + AT_B, g.nx), ye = min(y0 + AT_B, g.ny), ze = min(z0 + AT_B, g.nz);
+    // this lane's corner of the support box in centred voxel indices
     const int corner = tid & 7;
-    const float bcx = (float)((corner & 1) ? min(bxi * 16 + 15, g.nx - 1) + 1 : bxi * 16 - 1) - hx;
-    const float bcy = (float)((corner & 2) ? min(byi * 16 + 15, g.ny - 1) + 1 : byi * 16 - 1) - hy;
-    const float bcz = (float)((corner & 4) ? min(z0 + AT_NZ - 1, g.nz - 1) + 1 : z0 - 1) - hz;
+    const float bcx = (float)((corner & 1) ? xe : x0 - 1) - hx;
+    const float bcy = (float)((corner & 2) ? ye : y0 - 1) - hy;
+    const float bcz = (float)((corner & 4) ? ze : z0 - 1) - hz;
+    // the same box in (unbiased) index coordinates, for the clip
+    const float sx0 = (float)(x0 - 1), sx1 = (float)xe;
+    const float sy0 = (float)(y0 - 1), sy1 = (float)ye;
+    const float sz0 = (float)(z0 - 1), sz1 = (float)ze;
+    // biased coordinate -> halo-local cell: floor(X) - (x0 - 1) = (int)(X + 4) - (x0 + 3)
+    const int ox = x0 + (int)RAY_BIAS - 1, oy = y0 + (int)RAY_BIAS - 1, oz = z0 + (int)RAY_BIAS - 1;
     const TI *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
 
     for (int k = 0; k < g.n_proj; ++k) {
         const ConeBPView bv = bviews[k];
-        const ConeFPView &fv = fviews[k];
         const float rw = rcp_nr(dot4(bv.r[2], bcx, bcy, bcz));
         const float cu = dot4(bv.r[0], bcx, bcy, bcz) * rw, cv = dot4(bv.r[1], bcx, bcy, bcz) * rw;
         const int j_lo = max((int)floorf(min8(cu) + g.cu) - 1, 0), j_hi = min((int)floorf(max8(cu) + g.cu) + 2, g.nu - 1);
         const int i_lo = max((int)floorf(min8(cv) + g.cv) - 1, 0), i_hi = min((int)floorf(max8(cv) + g.cv) + 2, g.nv - 1);
         const int W = j_hi - j_lo + 1, H = i_hi - i_lo + 1;
-        const bool staged = W > 0 && H > 0 && W * H <= AT_RAYS;
-        const TI *qk = pb + (size_t)k * g.nv * g.nu;
-        __syncthreads();   // the previous view's table has been consumed
-        if (staged) {
-            for (int idx = tid; idx < W * H; idx += 256) {
-                const int ii = idx / W, jj = idx - ii * W;
-                const Ray r = make_cone_ray(g, fv, j_lo + jj, i_lo + ii);
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    rtab[t][idx] = r.p[t];
-                    rtab[3 + t][idx] = r.e[t];
-                }
-                rtab[6][idx] = g.step * load_f32(qk + (size_t)(i_lo + ii) * g.nu + (j_lo + jj));
-            }
-        }
-        __syncthreads();
-        if (!active || W <= 0 || H <= 0)
+        if (W <= 0 || H <= 0)
             continue;
-        // rays crossing this column's support: project its 8 corners
-        float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float cx = fx + ((c & 1) ? 1.0f : -1.0f) - hx, cy = fy + ((c & 2) ? 1.0f : -1.0f) - hy;
-            const float cz = (float)((c & 4) ? min(z0 + AT_NZ - 1, g.nz - 1) + 1 : z0 - 1) - hz;
-            const float w = rcp_nr(dot4(bv.r[2], cx, cy, cz));
-            const float uu = dot4(bv.r[0], cx, cy, cz) * w, vv = dot4(bv.r[1], cx, cy, cz) * w;
-            umin = fminf(umin, uu);
-            umax = fmaxf(umax, uu);
-            vmin = fminf(vmin, vv);
-            vmax = fmaxf(vmax, vv);
-        }
-        const int ja = max((int)floorf(umin + g.cu) - 1, j_lo), jb = min((int)floorf(umax + g.cu) + 2, j_hi);
-        const int ia = max((int)floorf(vmin + g.cv) - 1, i_lo), ib = min((int)floorf(vmax + g.cv) + 2, i_hi);
-        const float zlo = (float)(z0 - 1), zhi = (float)min(z0 + AT_NZ, g.nz);
-        for (int ii = ia; ii <= ib; ++ii) {
-            for (int jj = ja; jj <= jb; ++jj) {
-                float X0, Y0, Z0, eX, eY, eZ, gv;
-                if (staged) {
-                    const int idx = (ii - i_lo) * W + (jj - j_lo);
-                    X0 = rtab[0][idx];
-                    Y0 = rtab[1][idx];
-                    Z0 = rtab[2][idx];
-                    eX = rtab[3][idx];
-                    eY = rtab[4][idx];
-                    eZ = rtab[5][idx];
-                    gv = rtab[6][idx];
-                } else {
-                    const Ray r = make_cone_ray(g, fv, jj, ii);
-                    X0 = r.p[0];
-                    Y0 = r.p[1];
-                    Z0 = r.p[2];
-                    eX = r.e[0];
-                    eY = r.e[1];
-                    eZ = r.e[2];
-                    gv = g.step * load_f32(qk + (size_t)ii * g.nu + jj);
-                }
-                if (gv == 0.0f)
+        const ConeFPView &fv = fviews[k];
+        const TI *qk = pb + (size_t)k * g.nv * g.nu;
+        for (int idx = tid; idx < W * H; idx += 256) {
+            const int ii = idx / W, jj = idx - ii * W;
+            const int i = i_lo + ii, j = j_lo + jj;
+            const float gv = load_f32(qk + (size_t)i * g.nu + j);
+            if (gv == 0.0f)
+                continue;
+            const Ray r = make_cone_ray(g, fv, j, i);
+            // the samples that can reach the support: the clip only picks the
+            // range to visit (hardware reciprocals, widened by a step on each
+            // side); the exact cell test below decides every sample
+            float lo = -3.0e38f, hi = 3.0e38f;
+            if (!clip_line_rcp(r.p[0], r.e[0], sx0, sx1, lo, hi) || !clip_line_rcp(r.p[1], r.e[1], sy0, sy1, lo, hi) ||
+                !clip_line_rcp(r.p[2], r.e[2], sz0, sz1, lo, hi) || !(lo < hi + 0.01f))
+                continue;
+            const float Xb = r.p[0] + RAY_BIAS, Yb = r.p[1] + RAY_BIAS, Zb = r.p[2] + RAY_BIAS;
+            const double gd = (double)gv;
+            const int m1 = (int)ceilf(hi) + 1;
+            for (int m = (int)floorf(lo) - 1; m <= m1; ++m) {
+                // the projector's biased sample position (positive in the support)
+                const float X = ray_coord_biased(Xb, r.e[0], m), Y = ray_coord_biased(Yb, r.e[1], m),
+                            Z = ray_coord_biased(Zb, r.e[2], m);
+                if (!(X > 0.0f && Y > 0.0f && Z > 0.0f))
                     continue;
-                // the samples that can reach the support: the clip only picks
-                // the range to visit (hardware reciprocals, widened by a step
-                // on each side); the exact test below decides every sample
-                float lo = -3.0e38f, hi = 3.0e38f;
-                if (!clip_line_rcp(X0, eX, fx - 1.0f, fx + 1.0f, lo, hi) ||
-                    !clip_line_rcp(Y0, eY, fy - 1.0f, fy + 1.0f, lo, hi) || !clip_line_rcp(Z0, eZ, zlo, zhi, lo, hi) ||
-                    !(lo < hi + 0.01f))   // reciprocal error is below 1e-3 step at these ranges
+                const int cx = (int)X - ox, cy = (int)Y - oy, cz = (int)Z - oz;
+                if ((unsigned)max(cx, max(cy, cz)) > (unsigned)AT_B || min(cx, min(cy, cz)) < 0)
                     continue;
-                // the projector's biased sample positions, un-biased exactly
-                const float Xb = X0 + RAY_BIAS, Yb = Y0 + RAY_BIAS, Zb = Z0 + RAY_BIAS;
-                for (int m = (int)floorf(lo) - 1; m <= (int)ceilf(hi) + 1; ++m) {
-                    const float X = ray_coord_biased(Xb, eX, m) - RAY_BIAS;
-                    const float Y = ray_coord_biased(Yb, eY, m) - RAY_BIAS;
-                    const float Z = ray_coord_biased(Zb, eZ, m) - RAY_BIAS;
-                    const float w = gv * (1.0f - fabsf(X - fx)) * (1.0f - fabsf(Y - fy));
-                    if (!(fabsf(X - fx) < 1.0f && fabsf(Y - fy) < 1.0f))
-                        continue;
-                    const float fz = floorf(Z);
-                    const float tz = Z - fz;
-                    const int iz = (int)fz - z0;
-                    if (iz >= 0 && iz < AT_NZ)
-                        accl[iz][tid] = fmaf(w, 1.0f - tz, accl[iz][tid]);
-                    if (iz + 1 >= 0 && iz + 1 < AT_NZ)
-                        accl[iz + 1][tid] = fmaf(w, tz, accl[iz + 1][tid]);
-                }
+                const double tx = (double)__builtin_amdgcn_fractf(X), ty = (double)__builtin_amdgcn_fractf(Y),
+                             tz = (double)__builtin_amdgcn_fractf(Z);
+                const double a1 = gd * tz, a0 = gd - a1;
+                const double a01 = a0 * ty, a00 = a0 - a01, a11 = a1 * ty, a10 = a1 - a11;
+                double *c = acc + (cz * AT_H + cy) * AT_H + cx;
+                const double w001 = a00 * tx, w011 = a01 * tx, w101 = a10 * tx, w111 = a11 * tx;
+                atomicAdd(c, a00 - w001);
+                atomicAdd(c + 1, w001);
+                atomicAdd(c + AT_H, a01 - w011);
+                atomicAdd(c + AT_H + 1, w011);
+                atomicAdd(c + AT_H * AT_H, a10 - w101);
+                atomicAdd(c + AT_H * AT_H + 1, w101);
+                atomicAdd(c + AT_H * AT_H + AT_H, a11 - w111);
+                atomicAdd(c + AT_H * AT_H + AT_H + 1, w111);
             }
         }
     }
-    if (!active)
-        return;
-    T *out = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)iy * g.nx + ix;
-    for (int z = 0; z < AT_NZ && z0 + z < g.nz; ++z)
-        store_f32(out + (size_t)(z0 + z) * g.ny * g.nx, accl[z][tid]);
+    __syncthreads();
+    // write the brick's own cells (not the halo)
+    const size_t plane = (size_t)g.nx * g.ny;
+    T *vb = vol + (size_t)b * g.nz * plane;
+    for (int n = tid; n < AT_B * AT_B * AT_B; n += 256) {
+        const int lx = n % AT_B, ly = (n / AT_B) % AT_B, lz = n / (AT_B * AT_B);
+        const int ix = x0 + lx, iy = y0 + ly, iz = z0 + lz;
+        if (ix < g.nx && iy < g.ny && iz < g.nz)
+            store_f32(vb + (size_t)iz * plane + (size_t)iy * g.nx + ix,
+                      (float)((double)g.step * acc[((lz + 1) * AT_H + ly + 1) * AT_H + lx + 1]));
+    }
 }
 
 // --------------------------------------------------------------- B^T, 2D
@@ -310,9 +296,12 @@ template <typename T>
 hipError_t fpT_cone(const Geom3D &g, const ConeFPView *fviews, const ConeBPView *bviews, const void *proj, void *vol,
                     int batch, hipStream_t s)
 {
-    const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + AT_NZ - 1) / AT_NZ;
-    hipLaunchKernelGGL((fpT_cone_kernel<T, T>), dim3((unsigned)(nbx * nby * nzb * batch)), dim3(256), 0, s, g, fviews,
-                       bviews, (const T *)proj, (T *)vol, nbx, nby, nzb);
+    const int nbx = (g.nx + AT_B - 1) / AT_B, nby = (g.ny + AT_B - 1) / AT_B, nbz = (g.nz + AT_B - 1) / AT_B;
+    const long blocks = (long)nbx * nby * nbz * batch;
+    if (blocks > 0x7fffffffL)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((fpT_cone_kernel<T, T>), dim3((unsigned)blocks), dim3(256), 0, s, g, fviews, bviews,
+                       (const T *)proj, (T *)vol, nbx, nby, nbz);
     return hipGetLastError();
 }
 
