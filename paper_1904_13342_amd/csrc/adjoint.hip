@@ -2,13 +2,14 @@
 // ray-driven projector and the voxel-driven back-projector are an unmatched
 // pair; Eq. 4 and Sec. II.B.1 use A^T as A's gradient operator).
 //
-// A^T, the transpose of the fixed-step multilinear ray sampler, is computed
-// by gather and without atomics: voxel j receives
+// A^T, the transpose of the fixed-step multilinear ray sampler: voxel j
+// receives
 //     step * sum_r g_r * sum_k Lambda(X_rk - j),
 // Lambda the tensor-product hat function, X_rk the same FP32 sample positions
-// the forward projector uses.  In 2D a thread owns a pixel and walks, per
-// view, the rays that cross its support (j - 1, j + 1)^2.  In 3D a workgroup
-// owns a brick and its rays splat into an LDS accumulator (below).
+// the forward projector uses.  In 2D a thread owns a pixel and gathers, per
+// view, over the rays that cross its support (j - 1, j + 1)^2, without
+// atomics.  In 3D a workgroup owns a brick and its rays splat into an LDS
+// accumulator (below).
 //
 // B^T in 2D, the transpose of the voxel-driven distance-weighted
 // back-projector, scatters each pixel's value times dbeta * weight into the
@@ -91,25 +92,59 @@ __global__ void __launch_bounds__(256) fpT2d_kernel(Geom2D g, const float2 *__re
 
 // --------------------------------------------------------------- A^T, 3D
 //
-// A workgroup owns a 16 x 16 x 16 brick of voxels and accumulates its
-// transpose in LDS over every view, in FP64, with a one-voxel halo on each
-// side (18^3 cells): a sample whose trilinear support touches the brick adds
-// its eight corner weights there, and corners in the halo belong to the
-// neighbouring bricks, which see the same sample, so they are dropped.  Per
-// view, the rays that can reach the brick's support are the detector pixels
-// in the support box's footprint (its 8 corners projected by eight lanes and
-// reduced with DPP); each lane takes one ray, sets it up exactly as the
-// forward projector does (FP64 set-up, the same biased FP32 sample positions,
-// so the pair is transposed sample for sample), clips it to the support box
-// and walks its samples there once, splatting each with eight LDS FP64
-// atomic adds at fixed offsets from one cell address.  No barrier is needed
-// between views: the accumulator only ever receives atomic adds.  The brick
-// is written once at the end, so the output needs no clearing and no global
-// atomics.
+// A workgroup owns a 16 x 16 x 16 brick of voxels; each thread holds the
+// FP64 sums of one 16-voxel z-column of it in registers, over every view.
+// Per view, the rays that can reach the brick's support box (the detector
+// pixels of its footprint: 8 corners projected by eight lanes and reduced with
+// DPP) are set up exactly as the forward projector sets them up (FP64 set-up,
+// the same biased FP32 sample positions, so the pair is transposed sample for
+// sample) and clipped to the support box.  The rays are then counting-sorted
+// by their number of samples, so the 64 rays a wave walks together have
+// nearly equal lengths, and each lane walks one ray, splatting every sample's
+// eight trilinear corner weights into an LDS accumulator.
+//
+// The accumulator holds 32-bit fixed-point integers (u32 LDS atomics issue
+// in about half the time of FP64 ones, and integer sums are exact, so the
+// result does not depend on the order of the adds).  The scale of a pass is
+// set from its own rays: a sample's weight at one cell is at most 1, and the
+// samples of one ray add at most 1 / e_max + 1 at a cell (e_max its largest
+// per-step index increment), so no cell's sum exceeds
+//     bound = sum over rays of |g_r| (1 / e_max,r + 1),
+// and with scale = 2^30 / bound no cell can overflow.  Each corner term is
+// rounded to the nearest integer; after the pass every thread adds its own
+// cells, divided by the scale, to its FP64 sums and clears them.  The waves
+// take the sorted rays in tasks of 64 from a shared counter, longest first.  Cells of
+// the two-voxel halo are never read (the neighbouring bricks own those
+// voxels), so they need no clearing and may wrap.
+//
+// Sample ranges come from a clip with hardware reciprocals (relative error
+// ~1e-7 of a few thousand steps), widened by 0.01 step: every sample inside
+// the support box is visited, and a visited sample lies at most 0.01 step
+// outside it, so its cell stays inside the padded accumulator
+// (floor coordinates x0 - 2 .. x0 + 17).  Its rows and planes have odd
+// pitches: the rays of a wave, sorted by length, often sit at one x at the
+// same step, and even pitches would put their cells on a quarter of the
+// banks.
 
-constexpr int AT_B = 16;                 // brick edge (voxels)
-constexpr int AT_H = AT_B + 2;           // accumulator edge with the halo
-constexpr int AT_CELLS = AT_H * AT_H * AT_H;
+constexpr int AT_B = 16;                       // brick edge (voxels)
+constexpr int AT_P = AT_B + 4;                 // accumulator edge (cells)
+constexpr int AT_PY = AT_P + 1;                // row pitch (words)
+constexpr int AT_PZ = AT_P * AT_PY + 1;        // plane pitch (words)
+constexpr int AT_CELLS = AT_P * AT_PZ;
+constexpr int AT_RAYS = 536;                   // footprint pixels per pass (ray-table capacity; with the
+                                               // accumulator, three workgroups fit a CU's LDS)
+constexpr int AT_PER_THREAD = (AT_RAYS + 255) / 256;
+constexpr int AT_BINS = 256;                   // sample-count bins of the ray sort
+constexpr float AT_EPS = 0.01f;                // clip widening (steps)
+constexpr float AT_FIX = 1073741824.0f;        // 2^30
+
+// nearest integer of x (ties toward +inf) in one instruction
+__device__ __forceinline__ int round_to_int(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 
 template <typename T, typename TI>
 __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPView *__restrict__ fviews,
@@ -117,14 +152,32 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
                                                        const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
                                                        int nby, int nbz)
 {
-    __shared__ double acc[AT_CELLS];
-    const int tid = threadIdx.x;
+    __shared__ int acc[AT_CELLS];
+    __shared__ float4 s_ra[AT_RAYS];   // biased anchor X, Y, Z and the ray's value
+    __shared__ float4 s_rb[AT_RAYS];   // step e_x, e_y, e_z and the first sample (int bits)
+    __shared__ int s_cnt[AT_RAYS];
+    __shared__ int hist[AT_BINS];
+    __shared__ int s_wsum[4];
+    __shared__ float s_wbound[4];
+    __shared__ int s_nhit;
+    __shared__ int s_next;   // next 64-ray task of the walk
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int bxi = (int)(blockIdx.x % (unsigned)nbx), byi = (int)((blockIdx.x / (unsigned)nbx) % (unsigned)nby);
     const int bzb = (int)(blockIdx.x / (unsigned)(nbx * nby));
     const int bzi = bzb % nbz, b = bzb / nbz;
     const int x0 = bxi * AT_B, y0 = byi * AT_B, z0 = bzi * AT_B;
     for (int n = tid; n < AT_CELLS; n += 256)
-        acc[n] = 0.0;
+        acc[n] = 0;
+    hist[tid] = 0;
+    if (tid == 0)
+        s_next = 0;
+    // this thread's voxel column (x0 + lx, y0 + ly, z0 .. z0 + 15) and its cells
+    const int lx = tid % AT_B, ly = tid / AT_B;
+    const int own = 2 * AT_PZ + (ly + 2) * AT_PY + lx + 2;   // cell of (lx, ly, 0); + AT_PZ per z
+    double out[AT_B];
+#pragma unroll
+    for (int z = 0; z < AT_B; ++z)
+        out[z] = 0.0;
     __syncthreads();
 
     const float hx = 0.5f * (g.nx - 1), hy = 0.5f * (g.ny - 1), hz = 0.5f * (g.nz - 1);
@@ -141,8 +194,9 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
     const float sx0 = (float)(x0 - 1), sx1 = (float)xe;
     const float sy0 = (float)(y0 - 1), sy1 = (float)ye;
     const float sz0 = (float)(z0 - 1), sz1 = (float)ze;
-    // biased coordinate -> halo-local cell: floor(X) - (x0 - 1) = (int)(X + 4) - (x0 + 3)
-    const int ox = x0 + (int)RAY_BIAS - 1, oy = y0 + (int)RAY_BIAS - 1, oz = z0 + (int)RAY_BIAS - 1;
+    // biased floor coordinate -> accumulator cell: floor(X) - (x0 - 2) = (int)(X + 4) - (x0 + 2);
+    // the cell's byte address is 4 (iz PZ + iy PY + ix) + base (modulo 2^32)
+    const unsigned base = 0u - 4u * (unsigned)((z0 + 2) * AT_PZ + (y0 + 2) * AT_PY + (x0 + 2));
     const TI *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
 
     for (int k = 0; k < g.n_proj; ++k) {
@@ -156,59 +210,148 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
             continue;
         const ConeFPView &fv = fviews[k];
         const TI *qk = pb + (size_t)k * g.nv * g.nu;
-        for (int idx = tid; idx < W * H; idx += 256) {
-            const int ii = idx / W, jj = idx - ii * W;
-            const int i = i_lo + ii, j = j_lo + jj;
-            const float gv = load_f32(qk + (size_t)i * g.nu + j);
-            if (gv == 0.0f)
-                continue;
-            const Ray r = make_cone_ray(g, fv, j, i);
-            // the samples that can reach the support: the clip only picks the
-            // range to visit (hardware reciprocals, widened by a step on each
-            // side); the exact cell test below decides every sample
-            float lo = -3.0e38f, hi = 3.0e38f;
-            if (!clip_line_rcp(r.p[0], r.e[0], sx0, sx1, lo, hi) || !clip_line_rcp(r.p[1], r.e[1], sy0, sy1, lo, hi) ||
-                !clip_line_rcp(r.p[2], r.e[2], sz0, sz1, lo, hi) || !(lo < hi + 0.01f))
-                continue;
-            const float Xb = r.p[0] + RAY_BIAS, Yb = r.p[1] + RAY_BIAS, Zb = r.p[2] + RAY_BIAS;
-            const double gd = (double)gv;
-            const int m1 = (int)ceilf(hi) + 1;
-            for (int m = (int)floorf(lo) - 1; m <= m1; ++m) {
-                // the projector's biased sample position (positive in the support)
-                const float X = ray_coord_biased(Xb, r.e[0], m), Y = ray_coord_biased(Yb, r.e[1], m),
-                            Z = ray_coord_biased(Zb, r.e[2], m);
-                if (!(X > 0.0f && Y > 0.0f && Z > 0.0f))
+        const int nfp = W * H;
+        for (int c0 = 0; c0 < nfp; c0 += AT_RAYS) {
+            const int nc = min(AT_RAYS, nfp - c0);
+            // set-up: this thread's footprint pixels of the pass
+            float4 ra[AT_PER_THREAD], rb[AT_PER_THREAD];
+            int cnt[AT_PER_THREAD];
+            float lb = 0.0f;   // this thread's share of the bound
+#pragma unroll
+            for (int u = 0; u < AT_PER_THREAD; ++u) {
+                cnt[u] = 0;
+                const int idx = tid + 256 * u;
+                if (idx >= nc)
                     continue;
-                const int cx = (int)X - ox, cy = (int)Y - oy, cz = (int)Z - oz;
-                if ((unsigned)max(cx, max(cy, cz)) > (unsigned)AT_B || min(cx, min(cy, cz)) < 0)
+                const int f = c0 + idx, ii = f / W, jj = f - ii * W;
+                const int i = i_lo + ii, j = j_lo + jj;
+                const float gv = load_f32(qk + (size_t)i * g.nu + j);
+                if (gv == 0.0f)
                     continue;
-                const double tx = (double)__builtin_amdgcn_fractf(X), ty = (double)__builtin_amdgcn_fractf(Y),
-                             tz = (double)__builtin_amdgcn_fractf(Z);
-                const double a1 = gd * tz, a0 = gd - a1;
-                const double a01 = a0 * ty, a00 = a0 - a01, a11 = a1 * ty, a10 = a1 - a11;
-                double *c = acc + (cz * AT_H + cy) * AT_H + cx;
-                const double w001 = a00 * tx, w011 = a01 * tx, w101 = a10 * tx, w111 = a11 * tx;
-                atomicAdd(c, a00 - w001);
-                atomicAdd(c + 1, w001);
-                atomicAdd(c + AT_H, a01 - w011);
-                atomicAdd(c + AT_H + 1, w011);
-                atomicAdd(c + AT_H * AT_H, a10 - w101);
-                atomicAdd(c + AT_H * AT_H + 1, w101);
-                atomicAdd(c + AT_H * AT_H + AT_H, a11 - w111);
-                atomicAdd(c + AT_H * AT_H + AT_H + 1, w111);
+                const Ray r = make_cone_ray(g, fv, j, i);
+                float lo = -3.0e38f, hi = 3.0e38f;
+                if (!clip_line_rcp(r.p[0], r.e[0], sx0, sx1, lo, hi) ||
+                    !clip_line_rcp(r.p[1], r.e[1], sy0, sy1, lo, hi) ||
+                    !clip_line_rcp(r.p[2], r.e[2], sz0, sz1, lo, hi) || !(lo < hi + 2.0f * AT_EPS))
+                    continue;
+                const int m0 = (int)ceilf(lo - AT_EPS), m1 = (int)floorf(hi + AT_EPS);
+                if (m1 < m0)
+                    continue;
+                cnt[u] = m1 - m0 + 1;
+                ra[u] = make_float4(r.p[0] + RAY_BIAS, r.p[1] + RAY_BIAS, r.p[2] + RAY_BIAS, gv);
+                rb[u] = make_float4(r.e[0], r.e[1], r.e[2], __int_as_float(m0));
+                const float emax = fmaxf(fabsf(r.e[0]), fmaxf(fabsf(r.e[1]), fabsf(r.e[2])));
+                // 1 / e_max + 1, rounded up by a relative 1e-5 (the hardware reciprocal is within 1 ulp)
+                lb = fmaf(fabsf(gv), fmaf(__builtin_amdgcn_rcpf(emax), 1.00001f, 1.00001f), lb);
+                atomicAdd(&hist[min(cnt[u], AT_BINS - 1)], 1);
             }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+                lb += __shfl_xor(lb, o);
+            if (lane == 0)
+                s_wbound[wave] = lb;
+            __syncthreads();
+            // slots in descending order of sample count: bin AT_BINS - 1 - tid
+            // starts after the rays of all longer bins
+            {
+                const int bin = AT_BINS - 1 - tid;
+                const int v = hist[bin];
+                int x = v;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o);
+                    if (lane >= o)
+                        x += y;
+                }
+                if (lane == 63)
+                    s_wsum[wave] = x;
+                __syncthreads();
+                int off = 0;
+                for (int w = 0; w < wave; ++w)
+                    off += s_wsum[w];
+                hist[bin] = off + x - v;
+                if (tid == 255)
+                    s_nhit = off + x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < AT_PER_THREAD; ++u) {
+                if (cnt[u] > 0) {
+                    const int slot = atomicAdd(&hist[min(cnt[u], AT_BINS - 1)], 1);
+                    s_ra[slot] = ra[u];
+                    s_rb[slot] = rb[u];
+                    s_cnt[slot] = cnt[u];
+                }
+            }
+            __syncthreads();
+            const int nhit = s_nhit;
+            // summed in a fixed order: the result does not depend on the waves' timing
+            const float bound = (s_wbound[0] + s_wbound[1]) + (s_wbound[2] + s_wbound[3]);
+            if (nhit > 0) {   // uniform
+                const float scale = AT_FIX / bound;
+                // the waves take 64-ray tasks in order of decreasing ray length
+                for (;;) {
+                    int t = 0;
+                    if (lane == 0)
+                        t = atomicAdd(&s_next, 1);
+                    const int slot = __builtin_amdgcn_readfirstlane(t) * 64 + lane;
+                    if (slot - lane >= nhit)
+                        break;
+                    if (slot >= nhit)
+                        continue;
+                    const float4 A = s_ra[slot], E = s_rb[slot];
+                    const float gs = A.w * scale;
+                    float fm = (float)__float_as_int(E.w);
+                    const float fend = fm + (float)s_cnt[slot];
+                    for (; fm < fend; fm += 1.0f) {
+                        // the projector's biased sample position (positive: near the support box)
+                        const float X = fmaf(fm, E.x, A.x), Y = fmaf(fm, E.y, A.y), Z = fmaf(fm, E.z, A.z);
+                        const unsigned ix = (unsigned)X, iy = (unsigned)Y, iz = (unsigned)Z;
+                        const float tx = __builtin_amdgcn_fractf(X), ty = __builtin_amdgcn_fractf(Y),
+                                    tz = __builtin_amdgcn_fractf(Z);
+                        unsigned off = 4u * (__umul24(iz, AT_PZ) + __umul24(iy, AT_PY) + ix) + base;
+                        // the finished offset goes into one register, so the eight corners take
+                        // immediate offsets (otherwise the constant part is split off per corner)
+                        asm("" : "+v"(off));
+                        int *c = (int *)((char *)acc + off);
+                        const float a1 = gs * tz, a0 = gs - a1;
+                        const float a01 = a0 * ty, a00 = a0 - a01, a11 = a1 * ty, a10 = a1 - a11;
+                        // corner terms in fixed point, rounded to the nearest integer
+                        atomicAdd(c, round_to_int(fmaf(-a00, tx, a00)));
+                        atomicAdd(c + 1, round_to_int(a00 * tx));
+                        atomicAdd(c + AT_PY, round_to_int(fmaf(-a01, tx, a01)));
+                        atomicAdd(c + AT_PY + 1, round_to_int(a01 * tx));
+                        atomicAdd(c + AT_PZ, round_to_int(fmaf(-a10, tx, a10)));
+                        atomicAdd(c + AT_PZ + 1, round_to_int(a10 * tx));
+                        atomicAdd(c + AT_PZ + AT_PY, round_to_int(fmaf(-a11, tx, a11)));
+                        atomicAdd(c + AT_PZ + AT_PY + 1, round_to_int(a11 * tx));
+                    }
+                }
+                __syncthreads();
+                // fold this thread's cells into its FP64 sums and clear them
+                const double inv = 1.0 / (double)scale;
+#pragma unroll
+                for (int z = 0; z < AT_B; ++z) {
+                    const int n = own + z * AT_PZ;
+                    out[z] = fma((double)acc[n], inv, out[z]);
+                    acc[n] = 0;
+                }
+            }
+            hist[tid] = 0;
+            if (tid == 0)
+                s_next = 0;
+            __syncthreads();
         }
     }
-    __syncthreads();
-    // write the brick's own cells (not the halo)
+    // write the brick's own voxels
     const size_t plane = (size_t)g.nx * g.ny;
     T *vb = vol + (size_t)b * g.nz * plane;
-    for (int n = tid; n < AT_B * AT_B * AT_B; n += 256) {
-        const int lx = n % AT_B, ly = (n / AT_B) % AT_B, lz = n / (AT_B * AT_B);
-        const int ix = x0 + lx, iy = y0 + ly, iz = z0 + lz;
-        if (ix < g.nx && iy < g.ny && iz < g.nz)
-            store_f32(vb + (size_t)iz * plane + (size_t)iy * g.nx + ix,
-                      (float)((double)g.step * acc[((lz + 1) * AT_H + ly + 1) * AT_H + lx + 1]));
+    const int ix = x0 + lx, iy = y0 + ly;
+    if (ix < g.nx && iy < g.ny) {
+#pragma unroll
+        for (int z = 0; z < AT_B; ++z)
+            if (z0 + z < g.nz)
+                store_f32(vb + (size_t)(z0 + z) * plane + (size_t)iy * g.nx + ix, (float)((double)g.step * out[z]));
     }
 }
 
