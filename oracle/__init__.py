@@ -400,34 +400,16 @@ def adam(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 # ------------------------------------------------- TV-regularised iteration
 #
 # Sec. III.B.1 / Eq. 7: an additive layer holding the image, forward
-# projected, trained on the l2 data term plus lambda * TV.  TV is the
-# isotropic total variation with forward differences, no difference across
-# the last row / column / plane, and a smoothing constant eps.
+# projected, trained on the l2 data term plus lambda * TV.  Forward
+# differences D_d(q) = x[q + e_d] - x[q], zero where q + e_d leaves the grid.
+# Two readings: the isotropic total variation (the gradient magnitude per
+# voxel, smoothed by eps), and the anisotropic one, the sum of absolute
+# differences per axis, which is the total variation of the framework the
+# paper computes TV with (eps = 0 gives it exactly; eps > 0 smooths each
+# absolute value as sqrt(t^2 + eps^2)).
 
-def tv(x, eps):
-    """TV_eps(x) = sum_q sqrt(sum_d (x[q + e_d] - x[q])^2 + eps^2) over a 2D
-    [ny, nx] or 3D [nz, ny, nx] array; differences that would leave the grid
-    are zero."""
-    x = np.asarray(x, dtype=np.float64)
-    s = np.full(x.shape, eps * eps)
-    for ax in range(x.ndim):
-        d = np.zeros_like(x)
-        sl_hi = [slice(None)] * x.ndim
-        sl_lo = [slice(None)] * x.ndim
-        sl_hi[ax] = slice(1, None)
-        sl_lo[ax] = slice(0, -1)
-        d[tuple(sl_lo)] = x[tuple(sl_hi)] - x[tuple(sl_lo)]
-        s += d * d
-    return float(np.sqrt(s).sum())
-
-
-def tv_grad(x, eps):
-    """Gradient of ``tv``: for phi(q) the summand at q and D_d(q) its
-    differences, dTV/dx[p] = -sum_d D_d(p) / phi(p)
-    + sum_d [p - e_d in the grid] D_d(p - e_d) / phi(p - e_d)."""
-    x = np.asarray(x, dtype=np.float64)
+def _differences(x):
     D = []
-    s = np.full(x.shape, eps * eps)
     for ax in range(x.ndim):
         d = np.zeros_like(x)
         sl_hi = [slice(None)] * x.ndim
@@ -436,11 +418,46 @@ def tv_grad(x, eps):
         sl_lo[ax] = slice(0, -1)
         d[tuple(sl_lo)] = x[tuple(sl_hi)] - x[tuple(sl_lo)]
         D.append(d)
+    return D
+
+
+def tv(x, eps, anisotropic=False):
+    """Total variation of a 2D [ny, nx] or 3D [nz, ny, nx] array.
+    Isotropic: TV_eps(x) = sum_q sqrt(sum_d D_d(q)^2 + eps^2).
+    Anisotropic: sum_q sum_d sqrt(D_d(q)^2 + eps^2) (= sum |D_d(q)| at eps = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    D = _differences(x)
+    if anisotropic:
+        return float(sum(np.sqrt(d * d + eps * eps).sum() for d in D))
+    s = np.full(x.shape, eps * eps)
+    for d in D:
         s += d * d
-    phi = np.sqrt(s)
+    return float(np.sqrt(s).sum())
+
+
+def tv_grad(x, eps, anisotropic=False):
+    """Gradient of ``tv``.  With r_d(q) the derivative of the summand at q by
+    D_d(q) -- D_d(q) / phi(q), phi(q) the isotropic summand, or
+    D_d(q) / sqrt(D_d(q)^2 + eps^2) anisotropically (sign(D_d(q)) at eps = 0,
+    0 where D_d(q) = 0) --
+    dTV/dx[p] = -sum_d r_d(p) + sum_d [p - e_d in the grid] r_d(p - e_d)."""
+    x = np.asarray(x, dtype=np.float64)
+    D = _differences(x)
+    if anisotropic:
+        R = []
+        for d in D:
+            if eps > 0:
+                R.append(d / np.sqrt(d * d + eps * eps))
+            else:
+                R.append(np.sign(d))
+    else:
+        s = np.full(x.shape, eps * eps)
+        for d in D:
+            s += d * d
+        phi = np.sqrt(s)
+        R = [d / phi for d in D]
     g = np.zeros_like(x)
-    for ax, d in enumerate(D):
-        q = d / phi
+    for ax, q in enumerate(R):
         g -= q
         sl_hi = [slice(None)] * x.ndim
         sl_lo = [slice(None)] * x.ndim
