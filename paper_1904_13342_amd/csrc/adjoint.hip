@@ -138,14 +138,6 @@ constexpr int AT_BINS = 256;                   // sample-count bins of the ray s
 constexpr float AT_EPS = 0.01f;                // clip widening (steps)
 constexpr float AT_FIX = 1073741824.0f;        // 2^30
 
-// nearest integer of x (ties toward +inf) in one instruction
-__device__ __forceinline__ int round_to_int(float x)
-{
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
 template <typename T, typename TI>
 __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPView *__restrict__ fviews,
                                                        const ConeBPView *__restrict__ bviews,

@@ -275,9 +275,15 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
 // brick's footprint; the tile is then added to the projections with one global
 // float atomic per pixel.  FP32 in and out; the output must be zero on entry.
 //
-// The LDS tile accumulates in FP64: on gfx950 an FP64 LDS atomic add to
-// distinct addresses runs about twenty times faster than an FP32 one, which
-// the hardware serialises, and the sums come out more accurate besides.
+// The LDS tile accumulates 32-bit fixed-point integers: on gfx950 u32 LDS
+// atomic adds issue in about half the time of FP64 ones, and FP32 LDS atomic
+// adds are serialised per lane.  A view's scale is set so that no pixel can
+// overflow: each voxel adds at most |x| dbeta (SID/w)^2 to the tile in all
+// (its four bilinear weights sum to 1), w is at least the smallest depth of
+// the brick's corners in that view (w is affine in the position), so the
+// tile's total is bounded by (sum of |x| dbeta over the brick) times
+// (SID / w_min)^2.  Every term is rounded to the nearest integer; the flush
+// divides by the scale.
 // Equal addresses within one instruction still serialise, and columns lined
 // up along a ray land on the same detector column, so for circular views the
 // lanes of a wave are laid out across the rays: 16 columns on a line along
@@ -287,17 +293,19 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
 // instruction then hits 64 distinct pixels whenever neighbouring columns
 // project at least a pixel apart.
 
-// tile row stride (FP64 cells, >= BP_TW + 1): 160 dwords, so consecutive rows
-// start in opposite halves of the banks (measured fastest of 65, 66, 68, 72, 80)
-constexpr int BPT_TS = 80;
+// tile row stride (words, >= BP_TW + 1): 66, two banks on per row.  At
+// 512^3 strides of 2 mod 32 measured fastest (66 and 98: 36.4 ms) of 65-70,
+// 72-90 in steps of 4 and 97-100; odd strides took 42-47 ms, 68 and 100 54 ms.
+constexpr int BPT_TS = 66;
+constexpr float BPT_FIX = 2145386496.0f;   // 2^31 (1 - 2^-10)
 
-__device__ __forceinline__ void splat_tile(double *p, float x, float fu, float fv, int stride)
+__device__ __forceinline__ void splat_tile(int *p, float xs, float fu, float fv, int stride)
 {
-    const float a = x * (1.0f - fv), b = x * fv;
-    atomicAdd(p, (double)(a * (1.0f - fu)));
-    atomicAdd(p + 1, (double)(a * fu));
-    atomicAdd(p + stride, (double)(b * (1.0f - fu)));
-    atomicAdd(p + stride + 1, (double)(b * fu));
+    const float b = xs * fv, a = xs - b;
+    atomicAdd(p, round_to_int(fmaf(-a, fu, a)));
+    atomicAdd(p + 1, round_to_int(a * fu));
+    atomicAdd(p + stride, round_to_int(fmaf(-b, fu, b)));
+    atomicAdd(p + stride + 1, round_to_int(b * fu));
 }
 
 __device__ __forceinline__ void splat_global(float *q, const Geom3D &g, float su, float sv, float x)
@@ -337,25 +345,50 @@ __device__ __forceinline__ void splat_cell(float *q, const Geom3D &g, int j, int
 // The tile is cleared once per workgroup; each flush then reads and clears
 // the footprint it adds to the projections (splats never leave the
 // footprint), so the tile is zero again whenever the next view starts.
-__device__ __forceinline__ void clear_tile(double *tile, int tid)
+__device__ __forceinline__ void clear_tile(int *tile, int tid)
 {
     for (int n = tid; n < BP_TH * BPT_TS; n += 256)
-        tile[n] = 0.0;
+        tile[n] = 0;
 }
 
-__device__ __forceinline__ void flush_tile(double *tile, const Footprint &fp, const Geom3D &g, float *qk, int tid)
+__device__ __forceinline__ void flush_tile(int *tile, const Footprint &fp, const Geom3D &g, float *qk, float inv,
+                                           int tid)
 {
     for (int r = tid >> 4; r < fp.th; r += 16) {
         const int gi = fp.v_lo + r;
         const bool row_ok = (unsigned)gi < (unsigned)g.nv;
         for (int c = tid & 15; c < fp.tw; c += 16) {
             const int gj = fp.u_lo + c;
-            const float t = (float)tile[r * BPT_TS + c];
-            tile[r * BPT_TS + c] = 0.0;
-            if (t != 0.0f && row_ok && (unsigned)gj < (unsigned)g.nu)
-                unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, t);
+            const int t = tile[r * BPT_TS + c];
+            tile[r * BPT_TS + c] = 0;
+            if (t != 0 && row_ok && (unsigned)gj < (unsigned)g.nu)
+                unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, (float)t * inv);
         }
     }
+}
+
+// Sum of |x| dbeta over the brick's voxels, reduced over the workgroup in a
+// fixed order (the same on every run).
+__device__ __forceinline__ float brick_abs_sum(float s, float *red, int tid)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        s += __shfl_xor(s, o);
+    if ((tid & 63) == 0)
+        red[tid >> 6] = s;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Fixed-point scale of one view: BPT_FIX / (S (SID / w_min)^2), w_min the
+// smallest depth of the brick's corners (8 lanes, one corner each), widened
+// by a relative 1e-3 for the reciprocal's rounding.
+__device__ __forceinline__ float view_scale(const ConeBPView &v, const Geom3D &g, float cx, float cy, float cz,
+                                            float S)
+{
+    const float wmin = min8(dot4(v.r[2], cx, cy, cz));
+    const float sw = g.sid * __builtin_amdgcn_rcpf(wmin);
+    return BPT_FIX / (S * (sw * sw * 1.001f));
 }
 
 template <typename TI, int BP_NZ>
@@ -364,7 +397,8 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
                                                         int nbx, int nby, int nzb)
 {
     constexpr int ZQ = BP_NZ / 4;   // voxels in z per lane group
-    __shared__ double tile[BP_TH * BPT_TS];
+    __shared__ int tile[BP_TH * BPT_TS];
+    __shared__ float red[4];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int a = lane & 15, zq = lane >> 4;
@@ -386,6 +420,21 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
     float val[4][ZQ];
     int cur = -1;   // lane layout of val: 0 = lanes along y, 1 = lanes along x
+    float S = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int ix = bxi * 16 + 4 * wave + c, iy = byi * 16 + a;
+        if (ix < g.nx && iy < g.ny)
+#pragma unroll
+            for (int m = 0; m < ZQ; ++m) {
+                const int z = zq * ZQ + m;
+                if (z < zcount)
+                    S += fabsf(g.dbeta * load_f32(vb + ((size_t)z * g.ny + iy) * g.nx + ix));
+            }
+    }
+    S = brick_abs_sum(S, red, tid);
+    if (S == 0.0f)
+        return;   // the brick adds nothing (uniform)
     clear_tile(tile, tid);   // ordered before the first splat by the view loop's barrier
 
     for (int k = 0; k < g.n_proj; ++k) {
@@ -409,6 +458,7 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
         }
         const Footprint fp = brick_footprint(v, g, cx, cy, cz);
         const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
+        const float scale = view_scale(v, g, cx, cy, cz, S);
         float *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged)
             __syncthreads();   // the previous tile has been flushed and cleared
@@ -425,14 +475,15 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
                 const float sv0 = tile_coord(ac.vc0, g.cv, fp.v_lo);
                 const int iu = (int)su;
                 const float fu = __builtin_amdgcn_fractf(su);
-                double *col = tile + iu;
+                const float ws = wt * scale;
+                int *col = tile + iu;
 #pragma unroll
                 for (int m = 0; m < ZQ; ++m) {
                     const int z = zq * ZQ + m;
                     if (z < zcount) {
                         const float sv = fmaf((float)z, dvz, sv0);
                         const int iv = (int)sv;
-                        splat_tile(col + iv * BPT_TS, wt * val[c][m], fu, __builtin_amdgcn_fractf(sv), BPT_TS);
+                        splat_tile(col + iv * BPT_TS, ws * val[c][m], fu, __builtin_amdgcn_fractf(sv), BPT_TS);
                     }
                 }
             } else {
@@ -447,7 +498,7 @@ __global__ void __launch_bounds__(256) bpT_axial_kernel(Geom3D g, const ConeBPVi
         }
         if (staged) {
             __syncthreads();
-            flush_tile(tile, fp, g, qk, tid);
+            flush_tile(tile, fp, g, qk, 1.0f / scale, tid);
         }
     }
 }
@@ -459,7 +510,8 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
                                                           const TI *__restrict__ vol, float *__restrict__ proj,
                                                           int nbx, int nby, int nzb)
 {
-    __shared__ double tile[BP_TH * BPT_TS];
+    __shared__ int tile[BP_TH * BPT_TS];
+    __shared__ float red[4];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
     const unsigned lin = blockIdx.x;
@@ -484,6 +536,13 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
 #pragma unroll
     for (int z = 0; z < BP_NZ; ++z)
         val[z] = (active && z < zcount) ? g.dbeta * load_f32(src + (size_t)(z0 + z) * g.ny * g.nx) : 0.0f;
+    float S = 0.0f;
+#pragma unroll
+    for (int z = 0; z < BP_NZ; ++z)
+        S += fabsf(val[z]);
+    S = brick_abs_sum(S, red, tid);
+    if (S == 0.0f)
+        return;   // the brick adds nothing (uniform)
     float *pb = proj + (size_t)b * g.n_proj * g.nv * g.nu;
     clear_tile(tile, tid);   // ordered before the first splat by the view loop's barrier
 
@@ -491,6 +550,7 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
         const ConeBPView v = views[k];
         const Footprint fp = brick_footprint(v, g, cx, cy, cz);
         const bool staged = fp.tw <= BP_TW && fp.th <= BP_TH;
+        const float scale = view_scale(v, g, cx, cy, cz, S);
         float *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged)
             __syncthreads();   // the previous tile has been flushed and cleared
@@ -502,7 +562,7 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
                     const DetPoint d = general_point(v64, g, xc, yc, zc0 + (float)z, staged ? fp.u_lo : 0,
                                                      staged ? fp.v_lo : 0);
                     if (staged)
-                        splat_tile(tile + d.i * BPT_TS + d.j, d.wt * val[z], d.fu, d.fv, BPT_TS);
+                        splat_tile(tile + d.i * BPT_TS + d.j, d.wt * scale * val[z], d.fu, d.fv, BPT_TS);
                     else
                         splat_cell(qk, g, d.j, d.i, d.fu, d.fv, d.wt * val[z]);
                 }
@@ -510,7 +570,7 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
         }
         if (staged) {
             __syncthreads();
-            flush_tile(tile, fp, g, qk, tid);
+            flush_tile(tile, fp, g, qk, 1.0f / scale, tid);
         }
     }
 }

@@ -167,6 +167,15 @@ __device__ __forceinline__ float rcp_nr(float x)
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// nearest integer of x (ties toward +inf) in one instruction; the
+// fixed-point LDS accumulators of the transposes round every term with it
+__device__ __forceinline__ int round_to_int(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x)
 {
