@@ -251,6 +251,27 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
                   const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, ph_dtype dtype,
                   void *stream);
 
+/* ph_fdk_cone3d for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments without ws / ws_bytes and the same result, to the
+ * rounding of the sums, with no hipMalloc, hipFree or allocating library
+ * call.  Its scratch is a static device array of PH_FDK_STATIC_SCRATCH_BYTES
+ * per GPU, held from the first call on that GPU until the process ends: the
+ * per-view tables (back-projector rows, the default Ram-Lak response and
+ * redundancy weights, FFT twiddles), then the filtered projections of as
+ * many views as fit, which are back-projected in shares (each share adds to
+ * vol).  The tables are copied from the host, followed by a synchronisation
+ * of `stream`, whenever they differ from the ones the array holds.  Errors:
+ * PH_ERR_WORKSPACE when the tables and one view's filtered projections
+ * (batch * nv * nu * 4 bytes) do not fit, or when an FP16 / BF16 volume
+ * would need more than one share (a share adds to the stored volume, which
+ * half precision would round each time); the other errors as ph_fdk_cone3d.
+ * Every call on a GPU uses that GPU's one array: calls whose work overlaps
+ * on one GPU (other streams, other host threads) race. */
+#define PH_FDK_STATIC_SCRATCH_BYTES (64u << 20)
+int ph_fdk_cone3d_static(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
+                         const float *W_red, const float *W, int batch, ph_dtype dtype, void *stream);
+
 /* ------------------------------------------- learned corrector training
  * The FDK network of Eq. 5 with trainable projection-domain parameters:
  * Sec. III.A lets the redundancy weights be learned from a loss computed in

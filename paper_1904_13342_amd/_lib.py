@@ -90,6 +90,7 @@ SIGNATURES = {
     "ph_fbp_par2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fbp_fan2d": (_I, [_G2, _FP, _P, _P, _P, _I, _P, _P, _SZ, _I, _I, _P]),
     "ph_fdk_cone3d": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _P, _SZ, _I, _I, _P]),
+    "ph_fdk_cone3d_static": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "ph_filter_response": (_I, [_I, _I, ctypes.c_double, _FP]),
     "ph_filter_response_equiangular": (_I, [_I, ctypes.c_double, ctypes.c_double, _FP]),
     "ph_tv_3d": (_I, [_P, _I, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),

@@ -429,19 +429,19 @@ const float *equiangular_table(int M, double alpha, double sid, int nu, int *st)
     return (const float *)cached(key, [&] { return as_bytes(equiangular_response(M, alpha, sid, nu - 1)); }, st);
 }
 
+std::vector<float2> twiddles(int M)
+{
+    std::vector<float2> t((size_t)M);
+    for (int n = 0; n < M; ++n)
+        t[(size_t)n] = make_float2((float)std::cos(2.0 * kPi * n / M), (float)-std::sin(2.0 * kPi * n / M));
+    return t;
+}
+
 const float2 *twiddle_table(int M, int *st)
 {
     std::string key = "twiddle";
     append(key, &M, 1);
-    return (const float2 *)cached(
-        key,
-        [&] {
-            std::vector<float2> t((size_t)M);
-            for (int n = 0; n < M; ++n)
-                t[(size_t)n] = make_float2((float)std::cos(2.0 * kPi * n / M), (float)-std::sin(2.0 * kPi * n / M));
-            return as_bytes(t);
-        },
-        st);
+    return (const float2 *)cached(key, [&] { return as_bytes(twiddles(M)); }, st);
 }
 
 // Default redundancy weights: parallel pi/range; fan/cone 1/2 for a full
@@ -462,6 +462,29 @@ double parker(double beta, double gamma, double delta)
     return 0.0;
 }
 
+std::vector<float> wred_values(int kind, int n_proj, int nu, double du, double range, double sdd)
+{
+    std::vector<float> w((size_t)n_proj * nu);
+    const bool full = std::fabs(range - 2.0 * kPi) <= 1e-6 * 2.0 * kPi;
+    const double delta = 0.5 * (range - kPi);
+    for (int k = 0; k < n_proj; ++k) {
+        const double beta = range * k / n_proj;
+        for (int j = 0; j < nu; ++j) {
+            double v;
+            if (kind == 0)
+                v = kPi / range;
+            else if (full)
+                v = 0.5;
+            else if (kind == 3)   // equiangular bins: the fan angle is linear in j
+                v = parker(beta, (j - 0.5 * (nu - 1)) * du / sdd, delta);
+            else
+                v = parker(beta, std::atan((j - 0.5 * (nu - 1)) * du / sdd), delta);
+            w[(size_t)k * nu + j] = (float)v;
+        }
+    }
+    return w;
+}
+
 const float *wred_table(int kind, int n_proj, int nu, double du, double range, double sdd, int *st)
 {
     std::string key = "wred";
@@ -471,30 +494,7 @@ const float *wred_table(int kind, int n_proj, int nu, double du, double range, d
     append(key, &du, 1);
     append(key, &range, 1);
     append(key, &sdd, 1);
-    return (const float *)cached(
-        key,
-        [&] {
-            std::vector<float> w((size_t)n_proj * nu);
-            const bool full = std::fabs(range - 2.0 * kPi) <= 1e-6 * 2.0 * kPi;
-            const double delta = 0.5 * (range - kPi);
-            for (int k = 0; k < n_proj; ++k) {
-                const double beta = range * k / n_proj;
-                for (int j = 0; j < nu; ++j) {
-                    double v;
-                    if (kind == 0)
-                        v = kPi / range;
-                    else if (full)
-                        v = 0.5;
-                    else if (kind == 3)   // equiangular bins: the fan angle is linear in j
-                        v = parker(beta, (j - 0.5 * (nu - 1)) * du / sdd, delta);
-                    else
-                        v = parker(beta, std::atan((j - 0.5 * (nu - 1)) * du / sdd), delta);
-                    w[(size_t)k * nu + j] = (float)v;
-                }
-            }
-            return as_bytes(w);
-        },
-        st);
+    return (const float *)cached(key, [&] { return as_bytes(wred_values(kind, n_proj, nu, du, range, sdd)); }, st);
 }
 
 // --------------------------------------------------------- shared drivers
@@ -612,13 +612,11 @@ int filter_len(const float *K, int M, int nu, int *Mout)
 // the equiangular detector (2 is the cone beam).
 int kind2d(const ph_geom2d *g, bool fan) { return !fan ? 0 : g->fan_detector == 1 ? 3 : 1; }
 
-// Filter arguments of a validated call (M from filter_len); uploads the
-// default tables on first use.
-int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, double dv, double sid, double sdd,
-                double range, const float *K, int M, const float *W_red, const float *W, FilterArgs *a)
+// Scalar filter arguments of a validated call (M from filter_len); the
+// tables K, tw, W_red and W are left for the caller to set.
+void filter_scalars(int kind, int nu, int nv, int n_proj, int batch, double du, double dv, double sdd, int M,
+                    FilterArgs *a)
 {
-    int st = PH_OK;
-    const double tau = kind == 0 ? du : du * sid / sdd;
     a->nu = nu;
     a->nv = nv;
     a->n_proj = n_proj;
@@ -631,6 +629,16 @@ int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, doub
     a->cv = 0.5f * (float)(nv - 1);
     a->cos_sdd = kind == 0 ? 0.0f : (float)sdd;
     a->curved = kind == 3 ? 1 : 0;
+}
+
+// Filter arguments of a validated call (M from filter_len); uploads the
+// default tables on first use.
+int filter_args(int kind, int nu, int nv, int n_proj, int batch, double du, double dv, double sid, double sdd,
+                double range, const float *K, int M, const float *W_red, const float *W, FilterArgs *a)
+{
+    int st = PH_OK;
+    const double tau = kind == 0 ? du : du * sid / sdd;
+    filter_scalars(kind, nu, nv, n_proj, batch, du, dv, sdd, M, a);
     a->K = K ? K : kind == 3 ? equiangular_table(M, du / sdd, sid, nu, &st) : ramlak_table(M, tau, &st);
     if (st != PH_OK)
         return st;
@@ -783,6 +791,28 @@ int adjoint2d(const ph_geom2d *g, bool fan, bool of_projector, const float *rv, 
     if (st != PH_OK || !via_ws)
         return st;
     return to_status(launch_cast_from_f32(dtype, acc, out, n_out, (hipStream_t)stream));
+}
+
+// Tables held in the static scratch array of each device, as last copied
+// there: a call copies its tables only when they differ.
+std::mutex g_static_mu;
+std::vector<std::vector<unsigned char>> g_static_tables(64);
+
+int upload_static_tables(void *base, const std::vector<unsigned char> &host, hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= (int)g_static_tables.size())
+        return PH_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    std::vector<unsigned char> &held = g_static_tables[(size_t)dev];
+    if (held == host)
+        return PH_OK;
+    held.clear();
+    if (hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return PH_ERR_HIP;
+    held = host;
+    return PH_OK;
 }
 
 }  // namespace
@@ -1021,6 +1051,110 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
         return st;
     return to_status(launch_backproject_cone(dtype, G, (const ConeBPView *)views, views64_of(views, axial, g->n_proj),
                                              axial, bp_segment(g), q, true, vol, batch, (hipStream_t)stream));
+}
+
+int ph_fdk_cone3d_static(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
+                         const float *W_red, const float *W, int batch, ph_dtype dtype, void *stream)
+{
+    if (!proj || !vol)
+        return PH_ERR_NULL;
+    if (batch < 1)
+        return PH_ERR_SHAPE;
+    int st = check_dtype(dtype);
+    if (st != PH_OK)
+        return st;
+    Geom3D G;
+    std::vector<double> P;
+    st = validate3d(g, mats, &G, &P);
+    if (st != PH_OK)
+        return st;
+    st = filter_len(K, M, g->det_shape[1], &M);
+    if (st != PH_OK)
+        return st;
+    const int nu = g->det_shape[1], nv = g->det_shape[0], np = g->n_proj;
+    std::vector<ConeBPView> v;
+    std::vector<ConeBPView64> v64;
+    bool axial = false;
+    bp_views(g, P, &v, &axial, &v64);
+
+    // scratch layout: tables, then the filtered projections of a share of the views
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t o = off;
+        off = round_up(off + n);
+        return o;
+    };
+    const size_t o_views = take((size_t)np * sizeof(ConeBPView));
+    const size_t o_v64 = axial ? 0 : take((size_t)np * sizeof(ConeBPView64));
+    const size_t o_K = K ? 0 : take((size_t)M * sizeof(float));
+    const size_t o_tw = take((size_t)M * sizeof(float2));
+    const size_t o_wred = W_red ? 0 : take((size_t)np * nu * sizeof(float));
+    const size_t tables = off;
+    const size_t per_view = (size_t)batch * nv * nu * sizeof(float);
+    const size_t cap = (size_t)PH_FDK_STATIC_SCRATCH_BYTES;
+    if (tables >= cap || (cap - tables) / per_view < 1)
+        return PH_ERR_WORKSPACE;
+    const int share = (int)std::min<size_t>((size_t)np, (cap - tables) / per_view);
+    if (share < np && dtype != PH_F32)
+        return PH_ERR_WORKSPACE;
+
+    void *base = nullptr;
+    size_t bytes = 0;
+    if (static_scratch(&base, &bytes) != hipSuccess || bytes != cap)
+        return PH_ERR_HIP;
+    std::vector<unsigned char> host(tables, 0);
+    std::memcpy(host.data() + o_views, v.data(), (size_t)np * sizeof(ConeBPView));
+    if (!axial)
+        std::memcpy(host.data() + o_v64, v64.data(), (size_t)np * sizeof(ConeBPView64));
+    if (!K) {
+        const std::vector<float> k = ramlak_response(M, (double)g->det_spacing[1] * g->sid / g->sdd);
+        std::memcpy(host.data() + o_K, k.data(), k.size() * sizeof(float));
+    }
+    {
+        const std::vector<float2> t = twiddles(M);
+        std::memcpy(host.data() + o_tw, t.data(), t.size() * sizeof(float2));
+    }
+    if (!W_red) {
+        const std::vector<float> w = wred_values(2, np, nu, g->det_spacing[1], g->angular_range, g->sdd);
+        std::memcpy(host.data() + o_wred, w.data(), w.size() * sizeof(float));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = upload_static_tables(base, host, s);
+    if (st != PH_OK)
+        return st;
+
+    char *sb = (char *)base;
+    FilterArgs a;
+    filter_scalars(2, nu, nv, share, 1, g->det_spacing[1], g->det_spacing[0], g->sdd, M, &a);
+    a.K = K ? K : (const float *)(sb + o_K);
+    a.tw = (const float2 *)(sb + o_tw);
+    a.W = W;
+    const float *wred = W_red ? W_red : (const float *)(sb + o_wred);
+    const ConeBPView *views = (const ConeBPView *)(sb + o_views);
+    const ConeBPView64 *views64 = axial ? nullptr : (const ConeBPView64 *)(sb + o_v64);
+    float *q = (float *)(sb + tables);
+    const size_t elem = dtype == PH_F32 ? sizeof(float) : sizeof(uint16_t);
+    const int seg = bp_segment(g);
+    // views k0 .. k0 + kc - 1: filter each batch item's rows, then back-project
+    // the share (the first share overwrites vol, the others add to it)
+    for (int k0 = 0; k0 < np; k0 += share) {
+        const int kc = std::min(share, np - k0);
+        a.n_proj = kc;
+        a.W_red = wred + (size_t)k0 * nu;
+        for (int b = 0; b < batch; ++b) {
+            const char *in = (const char *)proj + ((size_t)b * np + k0) * nv * nu * elem;
+            st = to_status(launch_weight_filter(dtype, a, in, q + (size_t)b * kc * nv * nu, s));
+            if (st != PH_OK)
+                return st;
+        }
+        Geom3D Gk = G;
+        Gk.n_proj = kc;
+        st = to_status(launch_backproject_cone(dtype, Gk, views + k0, views64 ? views64 + k0 : nullptr, axial, seg, q,
+                                               true, vol, batch, s, k0 > 0));
+        if (st != PH_OK)
+            return st;
+    }
+    return PH_OK;
 }
 
 int ph_project_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,

@@ -104,10 +104,15 @@ hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *vie
 // nz_seg: voxels per thread column segment (16 or 32), chosen by the host
 // so that a brick's detector footprint fits the LDS tile (64 x 128 pixels).
 // views64: the FP64 rows of a trajectory that is not a rotation about z
-// (axial = false), NULL otherwise.
+// (axial = false), NULL otherwise.  accumulate: add to the volume instead of
+// overwriting it (back-projection of the views in shares).
 hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64,
                                    bool axial, int nz_seg, const void *proj, bool proj_is_f32, void *vol, int batch,
-                                   hipStream_t stream);
+                                   hipStream_t stream, bool accumulate = false);
+
+// The library's static scratch array on the current device (set up on first
+// use per device); PH_ERR_HIP-style failure returns a HIP error.
+hipError_t static_scratch(void **ptr, size_t *bytes);
 
 // Exact transposes.  A^T: any storage type (gather, written once).  B^T:
 // FP32 in and out (scatter with float atomics into a zero-filled output).

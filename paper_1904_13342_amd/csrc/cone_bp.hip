@@ -159,7 +159,7 @@ template <typename T, typename TI, int BP_NZ, bool AXIAL>
 __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView *__restrict__ views,
                                                       const ConeBPView64 *__restrict__ views64,
                                                       const TI *__restrict__ proj, T *__restrict__ vol, int nbx,
-                                                      int nby, int nzb)
+                                                      int nby, int nzb, int accumulate)
 {
     __shared__ float tile[BP_TH * BP_TS];
     const int tid = threadIdx.x;
@@ -262,9 +262,13 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
         return;
     T *out = vol + (size_t)b * g.nz * g.ny * g.nx + (size_t)iy * g.nx + ix;
 #pragma unroll
-    for (int z = 0; z < BP_NZ; ++z)
-        if (z < zcount)
-            store_f32(out + (size_t)(z0 + z) * g.ny * g.nx, g.dbeta * acc[z]);
+    for (int z = 0; z < BP_NZ; ++z) {
+        if (z < zcount) {
+            T *p = out + (size_t)(z0 + z) * g.ny * g.nx;
+            // accumulate: add to the volume (a later share of the views)
+            store_f32(p, accumulate ? load_f32(p) + g.dbeta * acc[z] : g.dbeta * acc[z]);
+        }
+    }
 }
 
 // ------------------------------------------------------------------- B^T
@@ -577,44 +581,45 @@ __global__ void __launch_bounds__(256) bpT_general_kernel(Geom3D g, const ConeBP
 
 template <typename T, typename TI, int NZ>
 hipError_t bp_cone_nz(const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64, bool axial,
-                      const void *proj, void *vol, int batch, hipStream_t s)
+                      const void *proj, void *vol, int batch, int acc, hipStream_t s)
 {
     const int nbx = (g.nx + 15) / 16, nby = (g.ny + 15) / 16, nzb = (g.nz + NZ - 1) / NZ;
     const unsigned blocks = (unsigned)(nbx * nby * nzb * batch);
     if (axial)
         hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, true>), dim3(blocks), dim3(256), 0, s, g, views,
-                           (const ConeBPView64 *)nullptr, (const TI *)proj, (T *)vol, nbx, nby, nzb);
+                           (const ConeBPView64 *)nullptr, (const TI *)proj, (T *)vol, nbx, nby, nzb, acc);
     else
         hipLaunchKernelGGL((bp_cone_kernel<T, TI, NZ, false>), dim3(blocks), dim3(256), 0, s, g, views, views64,
-                           (const TI *)proj, (T *)vol, nbx, nby, nzb);
+                           (const TI *)proj, (T *)vol, nbx, nby, nzb, acc);
     return hipGetLastError();
 }
 
 template <typename T, typename TI>
 hipError_t bp_cone(const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64, bool axial, int nz_seg,
-                   const void *proj, void *vol, int batch, hipStream_t s)
+                   const void *proj, void *vol, int batch, int acc, hipStream_t s)
 {
     if (!axial && !views64)
         return hipErrorInvalidValue;
     if (nz_seg >= 32)
-        return bp_cone_nz<T, TI, 32>(g, views, views64, axial, proj, vol, batch, s);
-    return bp_cone_nz<T, TI, 16>(g, views, views64, axial, proj, vol, batch, s);
+        return bp_cone_nz<T, TI, 32>(g, views, views64, axial, proj, vol, batch, acc, s);
+    return bp_cone_nz<T, TI, 16>(g, views, views64, axial, proj, vol, batch, acc, s);
 }
 
 }  // namespace
 
 hipError_t launch_backproject_cone(int dtype, const Geom3D &g, const ConeBPView *views, const ConeBPView64 *views64,
                                    bool axial, int nz_seg, const void *proj, bool proj_is_f32, void *vol, int batch,
-                                   hipStream_t stream)
+                                   hipStream_t stream, bool accumulate)
 {
+    const int a = accumulate ? 1 : 0;
     switch (dtype) {
-    case 0: return bp_cone<float, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
+    case 0: return bp_cone<float, float>(g, views, views64, axial, nz_seg, proj, vol, batch, a, stream);
     case 1:
-        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream)
-                           : bp_cone<f16_t, f16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<f16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, a, stream)
+                           : bp_cone<f16_t, f16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, a, stream);
     default:
-        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, stream)
-                           : bp_cone<bf16_t, bf16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, stream);
+        return proj_is_f32 ? bp_cone<bf16_t, float>(g, views, views64, axial, nz_seg, proj, vol, batch, a, stream)
+                           : bp_cone<bf16_t, bf16_t>(g, views, views64, axial, nz_seg, proj, vol, batch, a, stream);
     }
 }
 

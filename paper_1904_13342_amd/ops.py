@@ -499,6 +499,24 @@ def fdk_cone3d(g, mats, proj, K=None, M=None, W_red=None, W=None, out=None, ws=N
     return out
 
 
+def fdk_cone3d_static(g, mats, proj, out, K=None, M=None, W_red=None, W=None):
+    """ph_fdk_cone3d_static: FDK into the caller's ``out`` with the library's
+    static scratch (no device allocation in the library or here)."""
+    batch = _dev(proj, "proj", _sino_tail(g))
+    t = _traj(g, mats)
+    M = _filter_len(K, M)
+    nv, nu = g.det_shape[0], g.det_shape[1]
+    shape = (tuple(proj.shape[:1]) if proj.dim() == 4 else ()) + _vol_tail(g)
+    if tuple(out.shape) != shape or out.dtype != proj.dtype or out.device != proj.device or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {proj.dtype} tensor of shape {shape} on {proj.device}")
+    status = lib().ph_fdk_cone3d_static(ctypes.byref(g), _fptr(t), ctypes.c_void_p(proj.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _f32_dev(K, "K", M), M,
+                                        _f32_dev(W_red, "W_red", g.n_proj * nu), _f32_dev(W, "W", nv * nu), batch,
+                                        _DTYPES[proj.dtype], _stream(proj))
+    check("ph_fdk_cone3d_static", status)
+    return out
+
+
 def version():
     return lib().ph_version().decode()
 
@@ -510,7 +528,7 @@ __all__ = [
     "backproject_adjoint_fan2d", "backproject_adjoint_cone3d",
     "weight_filter_2d", "weight_filter_3d", "workspace_bytes_2d", "workspace_bytes_3d", "fdk_workspace_bytes",
     "fbp_par2d",
-    "fbp_fan2d", "fdk_cone3d", "filter_response", "filter_response_equiangular", "tv", "tv_workspace_bytes",
+    "fbp_fan2d", "fdk_cone3d", "fdk_cone3d_static", "filter_response", "filter_response_equiangular", "tv", "tv_workspace_bytes",
     "tv_iterate", "mse_grad",
     "corrector_grad_3d", "corrector_grad_2d", "adam_step", "version",
 ]

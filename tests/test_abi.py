@@ -187,6 +187,30 @@ def test_rejects_bad_filter_length_and_workspace(ph, L):
     assert L.ph_weight_filter_3d(ctypes.byref(g), FAKE, FAKE, None, 64, None, None, 1, 0, None) == -2
 
 
+def test_static_fdk_rejects_before_any_gpu_call(ph, L):
+    """ph_fdk_cone3d_static (the FDK that allocates nothing) validates like
+    ph_fdk_cone3d and refuses, on the host, sizes its static scratch cannot
+    take: one view's filtered projections larger than the scratch, and an
+    FP16 / BF16 volume that would need several shares of the views."""
+    g = _good3(ph)
+    mats = ph.projection_matrices_3d(g)
+    fp = mats.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    scratch = 64 << 20
+    assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, None, FAKE, None, 0, None, None, 1, 0, None) == -1
+    assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, 0, 0, None) == -2
+    assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, 1, 3, None) == -4
+    assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, FAKE, FAKE, FAKE, 100, None, None, 1, 0, None) == -2
+    # one view of a batch too large for the scratch
+    per_view = 48 * 48 * 4
+    big_batch = scratch // per_view + 1
+    assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, big_batch, 0, None) == -5
+    # half-precision volumes in more than one share
+    half_batch = scratch // (per_view * g.n_proj) + 1
+    for dt in (1, 2):
+        assert L.ph_fdk_cone3d_static(ctypes.byref(g), fp, FAKE, FAKE, None, 0, None, None, half_batch, dt,
+                                      None) == -5
+
+
 def test_rejects_bad_corrector_arguments(ph, L):
     g = _good3(ph)
     G = ctypes.byref(g)
