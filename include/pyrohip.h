@@ -338,17 +338,21 @@ int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, 
  * iteration is ph_project_* (A x), ph_mse_grad (residual gradient),
  * ph_project_adjoint_* (A^T), ph_tv_3d (regulariser) and ph_adam_step.
  *
- * Isotropic total variation with forward differences (none across the last
- * row / column / plane) and smoothing eps:
- *   TV(x) = sum_q sqrt(sum_d (x[q + e_d] - x[q])^2 + eps^2).
+ * Total variation with forward differences D_d(q) = x[q + e_d] - x[q] (none
+ * across the last row / column / plane) and smoothing eps:
+ *   anisotropic = 0: TV(x) = sum_q sqrt(sum_d D_d(q)^2 + eps^2)  (eps > 0);
+ *   anisotropic = 1: TV(x) = sum_q sum_d sqrt(D_d(q)^2 + eps^2) over the axes
+ *     of extent > 1, the sum of absolute differences at eps = 0 (eps >= 0;
+ *     the gradient takes sign(D), 0 at D = 0) -- the total variation of the
+ *     framework Sec. III.B.1 computes TV with.
  *   vol   : device float[batch][nz][ny][nx] (nz = 1 for an image [ny][nx]);
  *   grad  : device float, same shape, or NULL: grad += weight * dTV/dx;
  *   value : device double[batch] or NULL: TV of each item (FP32 terms summed
  *           in FP64 with atomics, so the last bits may vary).
- * eps > 0 and weight finite (else PH_ERR_VALUE); sizes and batch >= 1 (else
- * PH_ERR_SHAPE).  grad must not alias vol. */
-int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, float weight, float *grad,
-             double *value, void *stream);
+ * anisotropic 0 or 1, eps as above and weight finite (else PH_ERR_VALUE);
+ * sizes and batch >= 1 (else PH_ERR_SHAPE).  grad must not alias vol. */
+int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, int anisotropic, float eps, float weight,
+             float *grad, double *value, void *stream);
 
 /* n_iter iterations of the TV-regularised reconstruction in one call (the
  * five steps above, issued from the library without a host round trip):
@@ -360,11 +364,12 @@ int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, flo
  *              each item at the iterate before the last update.
  * The operator is the matched pair (A, A^T) of the geometry.  Validation as
  * for the operators; t0 >= 0, n_iter >= 1 (else PH_ERR_SHAPE); lam >= 0,
- * eps > 0, lr > 0, betas in [0, 1), adam_eps > 0, all finite (else
- * PH_ERR_VALUE). */
+ * eps as for ph_tv_3d, lr > 0, betas in [0, 1), adam_eps > 0, all finite,
+ * anisotropic 0 or 1 (else PH_ERR_VALUE). */
 typedef struct {
     float lam, eps;                      /* TV weight and smoothing */
     float lr, beta1, beta2, adam_eps;    /* Adam */
+    int anisotropic;                     /* 0: isotropic TV, 1: sum of absolute differences (as ph_tv_3d) */
 } ph_tv_params;
 
 size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch);

@@ -424,11 +424,13 @@ def _differences(x):
 def tv(x, eps, anisotropic=False):
     """Total variation of a 2D [ny, nx] or 3D [nz, ny, nx] array.
     Isotropic: TV_eps(x) = sum_q sqrt(sum_d D_d(q)^2 + eps^2).
-    Anisotropic: sum_q sum_d sqrt(D_d(q)^2 + eps^2) (= sum |D_d(q)| at eps = 0)."""
+    Anisotropic: sum_q sum_d sqrt(D_d(q)^2 + eps^2) (= sum |D_d(q)| at eps = 0)
+    over the axes d of extent > 1."""
     x = np.asarray(x, dtype=np.float64)
     D = _differences(x)
     if anisotropic:
-        return float(sum(np.sqrt(d * d + eps * eps).sum() for d in D))
+        # axes of extent 1 have no differences and add nothing
+        return float(sum(np.sqrt(d * d + eps * eps).sum() for ax, d in enumerate(D) if x.shape[ax] > 1))
     s = np.full(x.shape, eps * eps)
     for d in D:
         s += d * d

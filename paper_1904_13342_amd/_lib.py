@@ -50,7 +50,8 @@ class Geom3D(ctypes.Structure):
 class TvParams(ctypes.Structure):
     """Mirror of ph_tv_params."""
     _fields_ = [("lam", ctypes.c_float), ("eps", ctypes.c_float), ("lr", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("anisotropic", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -93,7 +94,7 @@ SIGNATURES = {
     "ph_fdk_cone3d_static": (_I, [_G3, _FP, _P, _P, _P, _I, _P, _P, _I, _I, _P]),
     "ph_filter_response": (_I, [_I, _I, ctypes.c_double, _FP]),
     "ph_filter_response_equiangular": (_I, [_I, ctypes.c_double, ctypes.c_double, _FP]),
-    "ph_tv_3d": (_I, [_P, _I, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "ph_tv_3d": (_I, [_P, _I, _I, _I, _I, _I, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "ph_tv_workspace_bytes_2d": (_SZ, [_G2, _I]),
     "ph_tv_workspace_bytes_3d": (_SZ, [_G3, _I]),
     "ph_tv_iterate_par2d": (_I, [_G2, _FP, _P, _P, _P, _P, _I, _I, ctypes.POINTER(TvParams), _P, _SZ, _P, _I, _P]),

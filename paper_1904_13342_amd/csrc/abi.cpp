@@ -1381,18 +1381,20 @@ int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, 
     return to_status(launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
 }
 
-int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, float eps, float weight, float *grad, double *value,
-             void *stream)
+int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, int anisotropic, float eps, float weight,
+             float *grad, double *value, void *stream)
 {
     if (!vol)
         return PH_ERR_NULL;
     if (nz < 1 || ny < 1 || nx < 1 || batch < 1 || (double)nx * ny * nz * batch > 1e12)
         return PH_ERR_SHAPE;
-    if (!(std::isfinite(eps) && eps > 0.0f) || !std::isfinite(weight))
+    if ((anisotropic != 0 && anisotropic != 1) || !std::isfinite(eps) || !(anisotropic ? eps >= 0.0f : eps > 0.0f) ||
+        !std::isfinite(weight))
         return PH_ERR_VALUE;
     if (!grad && !value)
         return PH_OK;
-    return to_status(launch_tv(vol, nx, ny, nz, batch, eps, weight, grad, value, (hipStream_t)stream));
+    return to_status(
+        launch_tv(vol, nx, ny, nz, batch, anisotropic != 0, eps, weight, grad, value, (hipStream_t)stream));
 }
 
 size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch)
@@ -1420,7 +1422,8 @@ namespace {
 bool tv_params_ok(const ph_tv_params *p)
 {
     auto fin = [](float v) { return std::isfinite(v); };
-    return fin(p->lam) && p->lam >= 0.0f && fin(p->eps) && p->eps > 0.0f && fin(p->lr) && p->lr > 0.0f &&
+    return (p->anisotropic == 0 || p->anisotropic == 1) && fin(p->lam) && p->lam >= 0.0f && fin(p->eps) &&
+           (p->anisotropic ? p->eps >= 0.0f : p->eps > 0.0f) && fin(p->lr) && p->lr > 0.0f &&
            fin(p->beta1) && p->beta1 >= 0.0f && p->beta1 < 1.0f && fin(p->beta2) && p->beta2 >= 0.0f &&
            p->beta2 < 1.0f && fin(p->adam_eps) && p->adam_eps > 0.0f;
 }
@@ -1457,8 +1460,8 @@ int tv_iterate(Fwd fwd, Adj adj, int nz, int ny, int nxg, size_t np, size_t nimg
         st = adj(gr, gx);
         if (st != PH_OK)
             return st;
-        st = to_status(launch_tv(x, nxg, ny, nz, batch, prm->eps, prm->lam, gx, last && data_tv ? data_tv + 1 : nullptr,
-                                 s));
+        st = to_status(launch_tv(x, nxg, ny, nz, batch, prm->anisotropic != 0, prm->eps, prm->lam, gx,
+                                 last && data_tv ? data_tv + 1 : nullptr, s));
         if (st != PH_OK)
             return st;
         st = to_status(launch_adam(x, gx, m, v, nimg, prm->lr, prm->beta1, prm->beta2, prm->adam_eps, t0 + it + 1, s));

@@ -172,7 +172,8 @@ hipError_t launch_adam(float *param, const float *grad, float *m, float *v, size
                        float eps, int t, hipStream_t stream);
 
 // Total variation (value and / or accumulated gradient)
-hipError_t launch_tv(const float *vol, int nx, int ny, int nz, int batch, float eps, float weight, float *grad,
-                     double *value, hipStream_t stream);
+// aniso: the sum of absolute differences per axis instead of the gradient magnitude
+hipError_t launch_tv(const float *vol, int nx, int ny, int nz, int batch, bool aniso, float eps, float weight,
+                     float *grad, double *value, hipStream_t stream);
 
 }  // namespace ph

@@ -29,15 +29,20 @@ class TVReconstruction:
     kind : "par2d", "fan2d" or "cone3d" (g and traj as for the operators);
     p    : FP32 device projections, [n_proj, nu] / [n_proj, nv, nu] or with a
            leading batch axis;
-    lam, eps : TV weight and smoothing; lr, betas, adam_eps : Adam.
+    lam, eps : TV weight and smoothing; lr, betas, adam_eps : Adam;
+    anisotropic : TV as the sum of absolute differences per axis (the
+           framework's own total variation the paper uses) instead of the
+           isotropic gradient magnitude.
     """
 
-    def __init__(self, kind, g, traj, p, lam=1e-3, eps=1e-3, lr=1e-2, betas=(0.9, 0.999), adam_eps=1e-8):
+    def __init__(self, kind, g, traj, p, lam=1e-3, eps=1e-3, lr=1e-2, betas=(0.9, 0.999), adam_eps=1e-8,
+                 anisotropic=False):
         if kind not in _PROJECT:
             raise ValueError(f"kind must be one of {sorted(_PROJECT)}")
         self.project, self.adjoint, self.dims = _PROJECT[kind]
         self.kind, self.g, self.traj, self.p = kind, g, traj, p
         self.lam, self.eps, self.lr, self.betas, self.adam_eps = lam, eps, lr, betas, adam_eps
+        self.anisotropic = bool(anisotropic)
         lead = tuple(p.shape[:-self.dims])   # batch axes (the projection tail has `dims` axes)
         shape = lead + tuple(g.vol_shape)
         self.x = torch.zeros(shape, dtype=torch.float32, device=p.device)
@@ -55,7 +60,7 @@ class TVReconstruction:
         self.project(self.g, self.traj, self.x, out=self._r)
         data, _ = ops.mse_grad(self._r, self.p, grad=self._gr)
         self.adjoint(self.g, self.traj, self._gr, out=self._gx)
-        tv, _ = ops.tv(self.x, self.eps, self.dims, weight=self.lam, grad=self._gx)
+        tv, _ = ops.tv(self.x, self.eps, self.dims, weight=self.lam, grad=self._gx, anisotropic=self.anisotropic)
         self.t += 1
         b1, b2 = self.betas
         ops.adam_step(self.x, self._gx, self.m, self.v, self.t, lr=self.lr, beta1=b1, beta2=b2, eps=self.adam_eps)
@@ -70,7 +75,8 @@ class TVReconstruction:
             self._ws = torch.empty(ops.tv_workspace_bytes(self.g, batch), dtype=torch.uint8, device=self.x.device)
         b1, b2 = self.betas
         out = ops.tv_iterate(self.kind, self.g, self.traj, self.p, self.x, self.m, self.v, self.t, iters, self.lam,
-                             self.eps, lr=self.lr, beta1=b1, beta2=b2, adam_eps=self.adam_eps, ws=self._ws)
+                             self.eps, lr=self.lr, beta1=b1, beta2=b2, adam_eps=self.adam_eps, ws=self._ws,
+                             anisotropic=self.anisotropic)
         self.t += iters
         return out
 

@@ -373,12 +373,13 @@ def adam_step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return param
 
 
-def tv(x, eps, dims, weight=1.0, grad=None, want_value=True):
-    """Isotropic total variation of x, whose last `dims` (2 or 3) axes are
-    spatial ([..., ny, nx] or [..., nz, ny, nx]) and the others a batch, FP32.
-    Returns (value, grad): value is a float64 device tensor with the batch
-    shape (a scalar when there is no batch axis); grad, when given, is
-    updated in place: grad += weight * dTV/dx."""
+def tv(x, eps, dims, weight=1.0, grad=None, want_value=True, anisotropic=False):
+    """Total variation of x, whose last `dims` (2 or 3) axes are spatial
+    ([..., ny, nx] or [..., nz, ny, nx]) and the others a batch, FP32:
+    isotropic, or with anisotropic=True the sum of absolute differences per
+    axis (eps = 0 allowed).  Returns (value, grad): value is a float64 device
+    tensor with the batch shape (a scalar when there is no batch axis); grad,
+    when given, is updated in place: grad += weight * dTV/dx."""
     if dims not in (2, 3):
         raise ValueError("dims must be 2 or 3")
     if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float32:
@@ -396,7 +397,8 @@ def tv(x, eps, dims, weight=1.0, grad=None, want_value=True):
         if grad.data_ptr() == x.data_ptr():
             raise ValueError("grad must not alias x")
     value = torch.empty(max(batch, 1), dtype=torch.float64, device=x.device) if want_value else None
-    status = lib().ph_tv_3d(ctypes.c_void_p(x.data_ptr()), nz, ny, nx, batch, float(eps), float(weight),
+    status = lib().ph_tv_3d(ctypes.c_void_p(x.data_ptr()), nz, ny, nx, batch, int(bool(anisotropic)), float(eps),
+                            float(weight),
                             None if grad is None else ctypes.c_void_p(grad.data_ptr()),
                             None if value is None else ctypes.c_void_p(value.data_ptr()), _stream(x))
     check("ph_tv_3d", status)
@@ -411,7 +413,7 @@ def tv_workspace_bytes(g, batch=1):
 
 
 def tv_iterate(kind, g, traj, proj, x, m, v, t0, n_iter, lam, eps, lr=1e-2, beta1=0.9, beta2=0.999, adam_eps=1e-8,
-               ws=None, data_tv=None):
+               ws=None, data_tv=None, anisotropic=False):
     """n_iter iterations of the TV-regularised reconstruction in one library
     call (x, m, v updated in place, Adam steps t0+1 .. t0+n_iter).  Returns
     data_tv, a float64 device tensor [1 + batch]: the data term and each
@@ -431,7 +433,8 @@ def tv_iterate(kind, g, traj, proj, x, m, v, t0, n_iter, lam, eps, lr=1e-2, beta
         ws = torch.empty(need, dtype=torch.uint8, device=proj.device)
     if data_tv is None:
         data_tv = torch.empty(1 + batch, dtype=torch.float64, device=proj.device)
-    prm = TvParams(float(lam), float(eps), float(lr), float(beta1), float(beta2), float(adam_eps))
+    prm = TvParams(float(lam), float(eps), float(lr), float(beta1), float(beta2), float(adam_eps),
+                   int(bool(anisotropic)))
     status = getattr(lib(), fns[kind])(ctypes.byref(g), _fptr(t), ctypes.c_void_p(proj.data_ptr()),
                                        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(m.data_ptr()),
                                        ctypes.c_void_p(v.data_ptr()), int(t0), int(n_iter), ctypes.byref(prm),

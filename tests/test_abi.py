@@ -238,12 +238,15 @@ def test_rejects_bad_corrector_arguments(ph, L):
 
 
 def test_rejects_bad_tv_arguments(L):
-    assert L.ph_tv_3d(None, 1, 4, 4, 1, 0.1, 1.0, FAKE, None, None) == -1
-    assert L.ph_tv_3d(FAKE, 0, 4, 4, 1, 0.1, 1.0, FAKE, None, None) == -2
-    assert L.ph_tv_3d(FAKE, 1, 4, 4, 0, 0.1, 1.0, FAKE, None, None) == -2
-    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.0, 1.0, FAKE, None, None) == -8
-    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.1, float("nan"), FAKE, None, None) == -8
-    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0.1, 1.0, None, None, None) == 0   # nothing requested: no launch
+    assert L.ph_tv_3d(None, 1, 4, 4, 1, 0, 0.1, 1.0, FAKE, None, None) == -1
+    assert L.ph_tv_3d(FAKE, 0, 4, 4, 1, 0, 0.1, 1.0, FAKE, None, None) == -2
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 0, 0, 0.1, 1.0, FAKE, None, None) == -2
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0, 0.0, 1.0, FAKE, None, None) == -8   # isotropic needs eps > 0
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 1, -0.1, 1.0, FAKE, None, None) == -8
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 2, 0.1, 1.0, FAKE, None, None) == -8
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0, 0.1, float("nan"), FAKE, None, None) == -8
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 0, 0.1, 1.0, None, None, None) == 0   # nothing requested: no launch
+    assert L.ph_tv_3d(FAKE, 1, 4, 4, 1, 1, 0.0, 1.0, None, None, None) == 0   # anisotropic: eps = 0 is valid
 
 
 def test_rejects_bad_tv_iterate_arguments(ph, L):
@@ -261,7 +264,8 @@ def test_rejects_bad_tv_iterate_arguments(ph, L):
     assert L.ph_tv_iterate_par2d(*args(ok, need, n=0)) == -2
     assert L.ph_tv_iterate_par2d(*args(ok, need, t0=-1)) == -2
     for bad in (TvParams(-1.0, 1e-2, 1e-2, 0.9, 0.999, 1e-8), TvParams(1e-3, 0.0, 1e-2, 0.9, 0.999, 1e-8),
-                TvParams(1e-3, 1e-2, 1e-2, 1.0, 0.999, 1e-8)):
+                TvParams(1e-3, 1e-2, 1e-2, 1.0, 0.999, 1e-8), TvParams(1e-3, -1e-2, 1e-2, 0.9, 0.999, 1e-8, 1),
+                TvParams(1e-3, 1e-2, 1e-2, 0.9, 0.999, 1e-8, 3)):
         assert L.ph_tv_iterate_par2d(*args(bad, need)) == -8
     assert L.ph_tv_iterate_par2d(G, fp, None, FAKE, FAKE, FAKE, 0, 5, ctypes.byref(ok), FAKE, need, None, 1,
                                  None) == -1

@@ -116,6 +116,15 @@ def test_aniso_equals_isotropic_for_one_axis_images(ora):
         assert np.allclose(ora.tv_grad(x, eps, anisotropic=True), ora.tv_grad(x, eps), rtol=1e-13, atol=1e-13)
 
 
+def test_aniso_axes_of_extent_one_add_nothing(ora):
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((7, 5))
+    for eps in (0.0, 0.1):
+        v = ora.tv(x, eps, anisotropic=True)
+        assert ora.tv(x[None], eps, anisotropic=True) == pytest.approx(v, rel=1e-14)
+        assert ora.tv(x[:, None, :], eps, anisotropic=True) == pytest.approx(v, rel=1e-14)
+
+
 def test_aniso_homogeneous_and_translation_invariant(ora):
     rng = np.random.default_rng(4)
     x = rng.standard_normal((5, 6, 7))
