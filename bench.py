@@ -93,6 +93,10 @@ def parse():
     ap.add_argument("--sigma", type=float, default=0.01, help="corrector: Gaussian noise on the line integrals")
     ap.add_argument("--lr", type=float, default=1e-3, help="corrector: Adam learning rate")
     ap.add_argument("--taps", type=int, default=1024, help="corrector: filter length M")
+    ap.add_argument("--k-init", choices=("ramp", "ramlak"), default="ramp",
+                    help="corrector: initial filter (the ramp, or Ram-Lak sampled on the M-point grid)")
+    ap.add_argument("--w-unit", type=float, default=1e-2,
+                    help="corrector: unit W is learned in (W moves by about lr * w_unit per step)")
     ap.add_argument("--save", default=None, help="corrector: write the learned K, W and losses to this .npz")
     return ap.parse_args()
 
@@ -190,7 +194,8 @@ def corrector_main(args):
     1 mm, 248 views over 200 deg, 620 x 480 detector at 1 mm): training
     phantoms are seeds 0..batch-1, projected by the library's own projector;
     every step adds fresh Gaussian noise and takes one Adam step on K (M taps,
-    ramp initialisation) and W (ones).  Held-out seeds 1000-1003 (noise drawn
+    ramp initialisation, learned in units of the ramp's bin step) and W (ones,
+    learned in units of 1e-2).  Held-out seeds 1000-1003 (noise drawn
     once) give the RMSE of the learned reconstruction, of the ramp
     initialisation, of plain Ram-Lak / Parker FDK and of Ram-Lak sampled on
     the learned filter's grid, over the whole volume and over the covered
@@ -235,7 +240,9 @@ def corrector_main(args):
             d = d[:, region]
         return float(d.mean().sqrt())
 
-    corr = ph.LearnedCorrector(g, mats, M=args.taps, lr=args.lr)
+    tau = spec.det_spacing[1] * spec.sid / spec.sdd
+    K0 = ph.filter_response(args.k_init, args.taps, tau) if args.k_init == "ramlak" else None
+    corr = ph.LearnedCorrector(g, mats, M=args.taps, K=K0, lr=args.lr, w_unit=args.w_unit)
     x_init = corr.reconstruct(p_test)
     x_plain = ph.fdk_cone3d(g, mats, p_test)
     tau = spec.det_spacing[1] * spec.sid / spec.sdd
@@ -274,7 +281,8 @@ def corrector_main(args):
         "dtype": "f32",
         "data": "synthetic: seeded random ellipsoids projected by the library's projector, Gaussian noise",
         "config": {"workload": f"cone3d 256^3 at 1 mm, {spec.n_proj} views over 200 deg, 620x480 detector at 1 mm",
-                   "batch": args.batch, "taps": args.taps, "sigma": args.sigma, "lr": args.lr},
+                   "batch": args.batch, "taps": args.taps, "sigma": args.sigma, "lr": args.lr,
+                   "K_init": args.k_init, "K_unit": corr.k_unit, "W_unit": corr.w_unit},
         "ms_per_step": float(np.mean(ms[1:] if len(ms) > 1 else ms)),
         "loss_first": losses[0],
         "loss_last10": float(np.mean(losses[-10:])),

@@ -29,21 +29,31 @@ class LearnedCorrector:
     M       : filter length (power of two, >= nu);
     K, W    : initial parameters (default: the ramp |f| on the DFT grid and
               ones), copied to FP32 device tensors;
-    lr, betas, eps : Adam hyper-parameters.
+    lr, betas, eps : Adam hyper-parameters;
+    k_unit, w_unit : the units K and W are learned in: Adam steps
+              theta = K / k_unit and omega = W / w_unit with lr and eps, so
+              K moves by about lr * k_unit per step and W by lr * w_unit.
+              k_unit defaults to 1 / (M tau), the ramp's step between
+              adjacent DFT bins (the ramp initialisation is min(f, M - f) in
+              it); w_unit to 1e-2.  1.0 learns a parameter in its own units.
     """
 
-    def __init__(self, g, mats, M=1024, K=None, W=None, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, device="cuda"):
+    def __init__(self, g, mats, M=1024, K=None, W=None, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, device="cuda",
+                 k_unit=None, w_unit=1e-2):
         self.g, self.mats = g, mats
         nv, nu = g.det_shape[0], g.det_shape[1]
         tau = g.det_spacing[1] * g.sid / g.sdd
         if K is None:
             K = ops.filter_response("ramp", M, tau)
+        M = K.numel()
+        self.k_unit = 1.0 / (M * tau) if k_unit is None else float(k_unit)
         self.K = K.detach().to(device=device, dtype=torch.float32).contiguous().clone()
         if W is None:
             W = torch.ones((nv, nu))
         self.W = W.detach().to(device=device, dtype=torch.float32).reshape(nv, nu).contiguous().clone()
         self.M = self.K.numel()
         self.lr, self.betas, self.eps = lr, betas, eps
+        self.w_unit = float(w_unit)
         self.mK, self.vK = torch.zeros_like(self.K), torch.zeros_like(self.K)
         self.mW, self.vW = torch.zeros_like(self.W), torch.zeros_like(self.W)
         self.t = 0
@@ -84,8 +94,13 @@ class LearnedCorrector:
         loss, dK, dW = self.gradients(proj, target, mask)
         self.t += 1
         b1, b2 = self.betas
-        ops.adam_step(self.K, dK, self.mK, self.vK, self.t, lr=self.lr, beta1=b1, beta2=b2, eps=self.eps)
-        ops.adam_step(self.W, dW, self.mW, self.vW, self.t, lr=self.lr, beta1=b1, beta2=b2, eps=self.eps)
+        # Adam on theta = K / k_unit, whose gradient is k_unit dK: Adam is
+        # invariant to the gradient's scale, so this is Adam on K with the
+        # step times k_unit and eps over k_unit (likewise for W)
+        ops.adam_step(self.K, dK, self.mK, self.vK, self.t, lr=self.lr * self.k_unit, beta1=b1, beta2=b2,
+                      eps=self.eps / self.k_unit)
+        ops.adam_step(self.W, dW, self.mW, self.vW, self.t, lr=self.lr * self.w_unit, beta1=b1, beta2=b2,
+                      eps=self.eps / self.w_unit)
         return loss.clone()
 
 

@@ -167,6 +167,45 @@ def test_training_step_gradient_parity(ph, ora):
     assert eK < FP32_TOL and eW < FP32_TOL
 
 
+def test_filter_step_is_adam_in_ramp_units(ph, ora):
+    """The corrector learns K in units of the ramp's bin step u = 1/(M tau)
+    and W in units of 1e-2: its step on K is Adam's step on theta = K / u
+    with gradient u dL/dK (oracle: FP64 Adam), and likewise for W."""
+    spec = SMALL
+    M = 128
+    p, ref = _training_problem(ora, spec, 2, 0)
+    g = ph.from_spec(spec)
+    corr = ph.LearnedCorrector(g, ph.projection_matrices_3d(g), M=M, lr=1e-3)
+    u = 1.0 / (M * ora.tau(spec))
+    wu = 1e-2
+    assert corr.k_unit == pytest.approx(u, rel=1e-6) and corr.w_unit == wu
+    K0, W0 = to_np(corr.K), to_np(corr.W)
+    _, dK, dW = corr.gradients(to_dev(p), to_dev(ref))
+    dK, dW = to_np(dK), to_np(dW)
+    corr.step(to_dev(p), to_dev(ref))
+    th1, _, _ = ora.adam(K0 / u, u * dK, np.zeros(M), np.zeros(M), 1, lr=1e-3, eps=1e-8)
+    om1, _, _ = ora.adam(W0 / wu, wu * dW, np.zeros_like(W0), np.zeros_like(W0), 1, lr=1e-3, eps=1e-8)
+    W1 = wu * om1
+    # Adam's first step is about lr * sign(g): compare where g is clearly
+    # nonzero.  K's step (lr u ~ 1e-5) is resolved only to the FP32 spacing of
+    # K itself, so the stored K is compared element by element within two
+    # spacings, and the step's size is bounded.
+    kk = np.abs(dK) > 1e-4 * np.abs(dK).max()
+    kw = np.abs(dW) > 1e-4 * np.abs(dW).max()
+    K1 = u * th1
+    spacing = np.spacing(np.abs(K1).astype(np.float32)).astype(np.float64)
+    dk = np.abs(to_np(corr.K) - K1)
+    spacing_w = np.spacing(np.abs(W1).astype(np.float32)).astype(np.float64)
+    dw = np.abs(to_np(corr.W) - W1)
+    say(f"[filter step] K: max |K - Adam on theta| {dk[kk].max():.3e} (<= 2 FP32 spacings: "
+        f"{bool(np.all(dk[kk] <= 2 * spacing[kk]))}), max step {np.abs(to_np(corr.K) - K0).max():.3e} "
+        f"(lr u = {1e-3 * u:.3e}); W: max |W - Adam on omega| {dw[kw].max():.3e}, max step "
+        f"{np.abs(to_np(corr.W) - W0).max():.3e}")
+    assert np.all(dk[kk] <= 2 * spacing[kk]) and np.all(dw[kw] <= 2 * spacing_w[kw])
+    assert np.abs(to_np(corr.K) - K0).max() <= 1e-3 * u * (1 + 1e-3)
+    assert np.abs(to_np(corr.W) - W0).max() <= 1e-3 * wu * (1 + 1e-3)
+
+
 def test_training_step_finite_differences(ph, ora):
     """The loss is quadratic in K and in W: central differences of the GPU
     loss along random directions reproduce the GPU gradient."""
@@ -226,7 +265,8 @@ def test_short_training_beats_ramp_initialisation(ph):
     def rmse(x):
         return float(((x.double() - x_test.double()) ** 2).mean().sqrt())
 
-    corr = ph.LearnedCorrector(g, mats, M=512, lr=1e-3)
+    # K and W in their own units: large steps, so 150 steps show the learning
+    corr = ph.LearnedCorrector(g, mats, M=512, lr=1e-3, k_unit=1.0, w_unit=1.0)
     r0 = rmse(corr.reconstruct(p_test))
     plain = rmse(ph.fdk_cone3d(g, mats, p_test))
     losses = []
