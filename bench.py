@@ -38,19 +38,35 @@ OPS_PER_UPDATE = 11.0      # back-projection: v coordinate, floor/fract, 3 lerps
 OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7 lerps, accumulate
 
 # HBM bytes per launch at 512^3 from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
-# what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524308 KiB, WRITE_SIZE 1048580 KiB).
+# what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524316 KiB, WRITE_SIZE 1048576 KiB).
 # A record holds for the kernel's device sources it was taken on (hash below); after any change to them the traffic
 # is reported as null.
 COPY_BYTES = 1 << 30
-COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.0, 1048580.0
+COPY_FETCH_KIB, COPY_WRITE_KIB = 524316.4, 1048576.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.23126e7, "write_kib": 1.23831e6,
-                "sources": ("cone_fp.hip", "device_util.h"), "sha256_16": "b2b7fab7ffe28763"},
-    "bp_cone": {"fetch_kib": 8.26492e6, "write_kib": 524288.0,
-                "sources": ("cone_bp.hip", "device_util.h"), "sha256_16": "32130d977583f1a2"},
-    "weight_filter": {"fetch_kib": 564813.0, "write_kib": 1.10592e6,
-                      "sources": ("filter.hip", "fft.h"), "sha256_16": "8b2cc952ec176687"},
+    "fp_cone": {"fetch_kib": 7.31957e+07, "write_kib": 1.23782e+06,
+               "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "f91a0caf53719f57"},
+    "bp_cone": {"fetch_kib": 8.56939e+06, "write_kib": 524288,
+               "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "75c200fb520e9dd7"},
+    "weight_filter": {"fetch_kib": 564843, "write_kib": 1.10592e+06,
+                     "sources": ('filter.hip', 'fft.h'), "sha256_16": "8b2cc952ec176687"},
+    "fpT_cone": {"fetch_kib": 8.47978e+06, "write_kib": 524288,
+                "sources": ('adjoint.hip', 'device_util.h'), "sha256_16": "45d833951596e357"},
+    "bpT_cone": {"fetch_kib": 2.8169e+06, "write_kib": 2.82697e+07,
+                "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "75c200fb520e9dd7"},
 }
+
+
+def add_hbm(kv, alg_bytes):
+    """HBM view of a VALU-bound kernel, beside its VALU roofline: algorithmic
+    bytes (inputs read once, outputs written once) and, where counters are on
+    record, the measured HBM bytes, each per launch time and as a fraction of
+    the 8 TB/s peak."""
+    s = kv["ms"] * 1e-3
+    kv["hbm"] = {"algorithmic_bytes": alg_bytes, "algorithmic_GBps": alg_bytes / s / 1e9,
+                 "algorithmic_frac": alg_bytes / s / 1e9 / PEAK_HBM_GBS,
+                 "measured_GBps": None if kv.get("traffic") is None else kv["traffic"] / s / 1e9,
+                 "measured_frac": None if kv.get("traffic") is None else kv["traffic"] / s / 1e9 / PEAK_HBM_GBS}
 
 
 def measured_traffic(name):
@@ -637,6 +653,7 @@ def adjoint_main(args):
         kernels[name] = {"bound": "alu", "ms": ms[name], "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
                          "frac": ach / PEAK_VALU_TOPS, "units_per_launch": units, "unit_name": uname,
                          "ops_per_unit": ops, "traffic": measured_traffic(name)}
+        add_hbm(kernels[name], 4 * (nx * ny * nz + spec.n_proj * int(np.prod(spec.det_shape))))
     dom_name = max(("fpT_cone", "bpT_cone"), key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     line = {
@@ -758,9 +775,13 @@ def main():
                     "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "units_per_launch": updates,
                     "unit_name": "voxel-view updates", "ops_per_unit": OPS_PER_UPDATE},
     }
+    vol_bytes, proj_bytes = 4 * nx * ny * nz, 4 * spec.n_proj * nv * nu
     for name, kv in kernels.items():
         kv["frac"] = kv["achieved"] / kv["peak"]
         kv["traffic"] = measured_traffic(name)
+    # the projector and back-projector are VALU-bound; their HBM figures are diagnostics
+    add_hbm(kernels["fp_cone"], vol_bytes + proj_bytes)
+    add_hbm(kernels["bp_cone"], vol_bytes + proj_bytes)
     dom_name = max(kernels, key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     roofline = {"kernel": dom_name, "bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"],

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -25,6 +26,12 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 // Derived per-view tables are uploaded once per (device, content) and kept
 // until the process ends (or evicted past kMaxEntries).  The key is the exact
 // bytes of everything the table depends on.
+//
+// Several host threads may call the library at once.  A table handed out by
+// cached() stays pinned by the calling thread until its entry point returns
+// (CallScope), by which time the kernels that read it are enqueued; eviction
+// only frees tables no thread has pinned, and hipFree waits for the device,
+// so a table is never freed between its lookup and the launch that uses it.
 
 struct Entry {
     int device;
@@ -32,8 +39,20 @@ struct Entry {
     void *ptr;
 };
 std::mutex g_mu;
-std::vector<Entry> g_cache;
+std::vector<std::shared_ptr<Entry>> g_cache;
 constexpr size_t kMaxEntries = 64;
+thread_local std::vector<std::shared_ptr<Entry>> t_pins;
+
+// Declared first in every entry point: releases the tables the call pinned.
+struct CallScope {
+    size_t mark;
+    CallScope() : mark(t_pins.size()) {}
+    ~CallScope()
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        t_pins.resize(mark);
+    }
+};
 
 template <typename Build>
 const void *cached(const std::string &key, Build build, int *status)
@@ -45,11 +64,12 @@ const void *cached(const std::string &key, Build build, int *status)
     }
     std::lock_guard<std::mutex> lock(g_mu);
     for (size_t n = 0; n < g_cache.size(); ++n) {
-        if (g_cache[n].device == dev && g_cache[n].key == key) {
-            Entry e = g_cache[n];
+        if (g_cache[n]->device == dev && g_cache[n]->key == key) {
+            std::shared_ptr<Entry> e = g_cache[n];
             g_cache.erase(g_cache.begin() + (long)n);
             g_cache.push_back(e);
-            return e.ptr;
+            t_pins.push_back(e);
+            return e->ptr;
         }
     }
     std::vector<unsigned char> host = build();
@@ -64,11 +84,19 @@ const void *cached(const std::string &key, Build build, int *status)
         return nullptr;
     }
     if (g_cache.size() >= kMaxEntries) {
-        // hipFree waits for outstanding work that may still read the entry
-        (void)hipFree(g_cache.front().ptr);
-        g_cache.erase(g_cache.begin());
+        // the least recently used table that no thread has pinned (hipFree
+        // waits for outstanding work that may still read it)
+        for (size_t n = 0; n < g_cache.size(); ++n) {
+            if (g_cache[n].use_count() == 1) {
+                (void)hipFree(g_cache[n]->ptr);
+                g_cache.erase(g_cache.begin() + (long)n);
+                break;
+            }
+        }
     }
-    g_cache.push_back(Entry{dev, key, p});
+    auto e = std::make_shared<Entry>(Entry{dev, key, p});
+    g_cache.push_back(e);
+    t_pins.push_back(e);
     return p;
 }
 
@@ -839,6 +867,7 @@ const char *ph_version(void) { return "pyrohip 0.1 (gfx950)"; }
 
 int ph_ray_vectors_2d(const ph_geom2d *g, float *ray_vecs)
 {
+    CallScope scope;
     if (!g || !ray_vecs)
         return PH_ERR_NULL;
     if (g->n_proj < 1)
@@ -855,6 +884,7 @@ int ph_ray_vectors_2d(const ph_geom2d *g, float *ray_vecs)
 
 int ph_projection_matrices_3d(const ph_geom3d *g, float *mats)
 {
+    CallScope scope;
     if (!g || !mats)
         return PH_ERR_NULL;
     if (g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1)
@@ -887,30 +917,35 @@ int ph_projection_matrices_3d(const ph_geom3d *g, float *mats)
 int ph_project_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, ph_dtype dtype,
                      void *stream)
 {
+    CallScope scope;
     return project2d(g, false, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_project_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch, ph_dtype dtype,
                      void *stream)
 {
+    CallScope scope;
     return project2d(g, true, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_backproject_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                          void *stream)
 {
+    CallScope scope;
     return backproject2d(g, false, rv, sino, img, batch, dtype, stream);
 }
 
 int ph_backproject_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                          void *stream)
 {
+    CallScope scope;
     return backproject2d(g, true, rv, sino, img, batch, dtype, stream);
 }
 
 int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch, ph_dtype dtype,
                       void *stream)
 {
+    CallScope scope;
     if (!vol || !proj)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -931,6 +966,7 @@ int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, vo
 int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch, ph_dtype dtype,
                           void *stream)
 {
+    CallScope scope;
     if (!vol || !proj)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -951,12 +987,14 @@ int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *pro
 int ph_weight_filter_2d(const ph_geom2d *g, int fan, const void *sino, float *out, const float *K, int M,
                         const float *W_red, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return weight_filter2d(g, fan != 0, sino, out, K, M, W_red, batch, dtype, stream);
 }
 
 int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const float *K, int M, const float *W_red,
                         const float *W, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     if (!proj || !out)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -981,6 +1019,7 @@ int ph_weight_filter_3d(const ph_geom3d *g, const void *proj, float *out, const 
 
 size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1)
         return 0;
     return round_up((size_t)batch * g->n_proj * g->det_shape * sizeof(float));
@@ -988,6 +1027,7 @@ size_t ph_workspace_bytes_2d(const ph_geom2d *g, int batch)
 
 size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1)
         return 0;
     return round_up((size_t)batch * g->n_proj * g->det_shape[0] * g->det_shape[1] * sizeof(float));
@@ -995,6 +1035,7 @@ size_t ph_workspace_bytes_3d(const ph_geom3d *g, int batch)
 
 size_t ph_fdk_workspace_bytes(const ph_geom3d *g, int M, int batch, ph_dtype dtype)
 {
+    CallScope scope;
     if (check_dtype(dtype) != PH_OK || !g || g->det_shape[1] < 1)
         return 0;
     // M = 0: the default Ram-Lak length; otherwise a length some response K may have
@@ -1006,18 +1047,21 @@ size_t ph_fdk_workspace_bytes(const ph_geom3d *g, int M, int batch, ph_dtype dty
 int ph_fbp_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
                  const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return fbp2d(g, false, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
 }
 
 int ph_fbp_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, const float *K, int M,
                  const float *W_red, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return fbp2d(g, true, rv, sino, img, K, M, W_red, ws, ws_bytes, batch, dtype, stream);
 }
 
 int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
                   const float *W_red, const float *W, void *ws, size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     if (!proj || !vol)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1056,6 +1100,7 @@ int ph_fdk_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void 
 int ph_fdk_cone3d_static(const ph_geom3d *g, const float *mats, const void *proj, void *vol, const float *K, int M,
                          const float *W_red, const float *W, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     if (!proj || !vol)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1160,30 +1205,35 @@ int ph_fdk_cone3d_static(const ph_geom3d *g, const float *mats, const void *proj
 int ph_project_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                              void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, false, true, rv, sino, img, batch, dtype, stream);
 }
 
 int ph_project_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *sino, void *img, int batch, ph_dtype dtype,
                              void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, true, true, rv, sino, img, batch, dtype, stream);
 }
 
 int ph_backproject_adjoint_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
                                  ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_backproject_adjoint_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, int batch,
                                  ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream);
 }
 
 int ph_project_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch,
                               ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     if (!proj || !vol)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1246,11 +1296,13 @@ static int bpT3d(const ph_geom3d *g, const float *mats, const void *vol, void *p
 int ph_backproject_adjoint_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, int batch,
                                   ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return bpT3d(g, mats, vol, proj, nullptr, 0, false, batch, dtype, stream);
 }
 
 size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, ph_dtype dtype)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1 || check_dtype(dtype) != PH_OK || dtype == PH_F32)
         return 0;
     return round_up((size_t)batch * g->n_proj * g->det_shape * sizeof(float));
@@ -1258,6 +1310,7 @@ size_t ph_backproject_adjoint_workspace_bytes_2d(const ph_geom2d *g, int batch, 
 
 size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, ph_dtype dtype)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1 || check_dtype(dtype) != PH_OK ||
         dtype == PH_F32)
         return 0;
@@ -1267,23 +1320,27 @@ size_t ph_backproject_adjoint_workspace_bytes_3d(const ph_geom3d *g, int batch, 
 int ph_backproject_adjoint_ws_par2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
                                     size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, false, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
 }
 
 int ph_backproject_adjoint_ws_fan2d(const ph_geom2d *g, const float *rv, const void *img, void *sino, void *ws,
                                     size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return adjoint2d(g, true, false, rv, img, sino, batch, dtype, stream, ws, ws_bytes, true);
 }
 
 int ph_backproject_adjoint_ws_cone3d(const ph_geom3d *g, const float *mats, const void *vol, void *proj, void *ws,
                                      size_t ws_bytes, int batch, ph_dtype dtype, void *stream)
 {
+    CallScope scope;
     return bpT3d(g, mats, vol, proj, ws, ws_bytes, true, batch, dtype, stream);
 }
 
 int ph_filter_response_equiangular(int M, double alpha, double sid, float *K)
 {
+    CallScope scope;
     if (!K)
         return PH_ERR_NULL;
     if (!is_pow2(M) || M < 2 || M > 4096)
@@ -1297,6 +1354,7 @@ int ph_filter_response_equiangular(int M, double alpha, double sid, float *K)
 
 int ph_filter_response(int kind, int M, double tau, float *K)
 {
+    CallScope scope;
     if (!K)
         return PH_ERR_NULL;
     if (!is_pow2(M) || M < 2 || M > 4096)
@@ -1315,6 +1373,7 @@ int ph_filter_response(int kind, int M, double tau, float *K)
 
 int ph_mse_grad(const float *x, const float *ref, const float *mask, size_t n, float *grad, double *loss, void *stream)
 {
+    CallScope scope;
     if (!x || !ref || !grad || !loss)
         return PH_ERR_NULL;
     if (n < 1)
@@ -1325,6 +1384,7 @@ int ph_mse_grad(const float *x, const float *ref, const float *mask, size_t n, f
 int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *grad_q, const float *K, int M,
                          const float *W_red, const float *W, float *dK, float *dW, int batch, void *stream)
 {
+    CallScope scope;
     if (!proj || !grad_q || !K || !dK)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1347,6 +1407,7 @@ int ph_corrector_grad_3d(const ph_geom3d *g, const float *proj, const float *gra
 int ph_corrector_grad_2d(const ph_geom2d *g, int fan, const float *sino, const float *grad_q, const float *K, int M,
                          const float *W_red, float *dK, int batch, void *stream)
 {
+    CallScope scope;
     if (!sino || !grad_q || !K || !dK)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1369,6 +1430,7 @@ int ph_corrector_grad_2d(const ph_geom2d *g, int fan, const float *sino, const f
 int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, float lr, float beta1, float beta2,
                  float eps, int t, void *stream)
 {
+    CallScope scope;
     if (!param || !grad || !m || !v)
         return PH_ERR_NULL;
     if (n < 1)
@@ -1384,6 +1446,7 @@ int ph_adam_step(float *param, const float *grad, float *m, float *v, size_t n, 
 int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, int anisotropic, float eps, float weight,
              float *grad, double *value, void *stream)
 {
+    CallScope scope;
     if (!vol)
         return PH_ERR_NULL;
     if (nz < 1 || ny < 1 || nx < 1 || batch < 1 || (double)nx * ny * nz * batch > 1e12)
@@ -1399,6 +1462,7 @@ int ph_tv_3d(const float *vol, int nz, int ny, int nx, int batch, int anisotropi
 
 size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape < 1 || g->vol_shape[0] < 1 || g->vol_shape[1] < 1)
         return 0;
     const size_t np = (size_t)batch * g->n_proj * g->det_shape, nx = (size_t)batch * g->vol_shape[0] * g->vol_shape[1];
@@ -1407,6 +1471,7 @@ size_t ph_tv_workspace_bytes_2d(const ph_geom2d *g, int batch)
 
 size_t ph_tv_workspace_bytes_3d(const ph_geom3d *g, int batch)
 {
+    CallScope scope;
     if (!g || batch < 1 || g->n_proj < 1 || g->det_shape[0] < 1 || g->det_shape[1] < 1 || g->vol_shape[0] < 1 ||
         g->vol_shape[1] < 1 || g->vol_shape[2] < 1)
         return 0;
@@ -1479,6 +1544,7 @@ int ph_tv_iterate_par2d(const ph_geom2d *g, const float *rv, const float *proj, 
                         int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv, int batch,
                         void *stream)
 {
+    CallScope scope;
     if (!g)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1500,6 +1566,7 @@ int ph_tv_iterate_fan2d(const ph_geom2d *g, const float *rv, const float *proj, 
                         int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv, int batch,
                         void *stream)
 {
+    CallScope scope;
     if (!g)
         return PH_ERR_NULL;
     if (batch < 1)
@@ -1521,6 +1588,7 @@ int ph_tv_iterate_cone3d(const ph_geom3d *g, const float *mats, const float *pro
                          int t0, int n_iter, const ph_tv_params *prm, void *ws, size_t ws_bytes, double *data_tv,
                          int batch, void *stream)
 {
+    CallScope scope;
     if (!g)
         return PH_ERR_NULL;
     if (batch < 1)
