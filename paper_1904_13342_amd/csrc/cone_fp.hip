@@ -14,6 +14,8 @@
 // with all eight trilinear corners read from LDS.  A sample belongs to
 // exactly one slab, decided by the same FP32 coordinate the interpolation
 // uses.  Slabs that do not fit in LDS read the volume directly.
+#include <type_traits>
+
 #include "device_util.h"
 
 namespace ph {
@@ -46,16 +48,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_run(const void *base, un
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
-template <typename T> __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s);
-template <> __device__ __forceinline__ float buf_f32<f16_t>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s)
-{
-    return (float)__builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0));
-}
-template <> __device__ __forceinline__ float buf_f32<bf16_t>(__amdgpu_buffer_rsrc_t r, unsigned v, unsigned s)
-{
-    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0) << 16);
-}
-
 __device__ __forceinline__ bool krange(float p, float e, int n, float &lo, float &hi)
 {
     if (fabsf(e) < 1e-30f)
@@ -118,8 +110,9 @@ __device__ __forceinline__ float sample_lds(const float *slab, float fm, float P
 // fixed (a, b) cells and walks them up through the z planes.  Planes outside
 // the grid are zero; the rest are read through buffer descriptors over runs
 // of eight planes (plane offsets are uniform, the cell's byte offset is per
-// lane).  FP32 loads write LDS directly and are still in flight on return
-// (the caller waits); other storage types are converted through registers.
+// lane) straight into LDS, one word per cell, and are still in flight on
+// return (the caller waits).  A 16-bit load leaves its value zero-extended in
+// the low half of the cell's word; widen_slab then makes the words FP32.
 template <typename T, int AX>
 __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *buf, int a0, int b_lo, int c_lo, int HB,
                                            int HC, int tid)
@@ -130,83 +123,61 @@ __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *b
     const size_t zstride = (size_t)g.nx * g.ny;
     const unsigned zbytes = (unsigned)(zstride * sizeof(T));
     const T *fz = f + (size_t)z_lo * zstride;
-    if constexpr (sizeof(T) == 4) {
-        // cell q of a plane is LDS word q, so a wave fills 64 consecutive
-        // words per plane; columns outside the grid are zeroed
-        for (int q = tid; q < plane; q += 256) {
-            const int ib = q / FP_WA, ia = q - ib * FP_WA;
-            const int ga = a0 + ia, gb = b_lo + ib;
-            const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
-            const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
-            float *dst = buf + q;
-            for (int ic = 0; ic < n_below; ++ic)
-                dst[ic * plane] = 0.0f;
-            for (int ic = n_below + n_in; ic < HC; ++ic)
-                dst[ic * plane] = 0.0f;
-            if (in_xy) {
-                const unsigned xy = (unsigned)(gy * g.nx + gx) * 4u;
-                // first word of this wave's run of 64 cells
-                float *wrun = buf + __builtin_amdgcn_readfirstlane(q & ~63);
-                const T *src = fz;
-                for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
-                    const int cnt = min(n_in - ic0, 8);
-                    const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
-                    float *wd = wrun + (n_below + ic0) * plane;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (u < cnt)   // uniform
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                rs, (__attribute__((address_space(3))) void *)(wd + u * plane), 4, xy,
-                                (unsigned)u * zbytes, 0, 0);
-                    src += 8 * zstride;
-                }
-            } else {
-                for (int ic = n_below; ic < n_below + n_in; ++ic)
-                    dst[ic * plane] = 0.0f;
-            }
-        }
-    } else {
-        // rows along x (the fastest axis in memory) keep the loads coalesced
-        const int L = AX == 0 ? FP_WA : HB;   // x-run length
-        const float invL = 1.0f / (float)L;
-        for (int q = tid; q < plane; q += 256) {
-            int row = (int)(((float)q + 0.5f) * invL);   // quotient, corrected to exact
-            int col = q - row * L;
-            row += (col >= L) - (col < 0);
-            col = q - row * L;
-            const int ia = AX == 0 ? col : row, ib = AX == 0 ? row : col;
-            const int ga = a0 + ia, gb = b_lo + ib;
-            const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
-            const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
-            const unsigned xy = in_xy ? (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T) : 0u;
-            float *dst = buf + ib * FP_WA + ia;
-            for (int ic = 0; ic < n_below; ++ic)
-                dst[ic * plane] = 0.0f;
-            float *d = dst + n_below * plane;
+    // cell q of a plane is LDS word q, so a wave fills 64 consecutive words
+    // per plane; columns outside the grid are zeroed
+    for (int q = tid; q < plane; q += 256) {
+        const int ib = q / FP_WA, ia = q - ib * FP_WA;
+        const int ga = a0 + ia, gb = b_lo + ib;
+        const int gx = AX == 0 ? ga : gb, gy = AX == 0 ? gb : ga;
+        const bool in_xy = (unsigned)gx < (unsigned)g.nx && (unsigned)gy < (unsigned)g.ny;
+        float *dst = buf + q;
+        for (int ic = 0; ic < n_below; ++ic)
+            dst[ic * plane] = 0.0f;
+        for (int ic = n_below + n_in; ic < HC; ++ic)
+            dst[ic * plane] = 0.0f;
+        if (in_xy) {
+            const unsigned xy = (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T);
+            // first word of this wave's run of 64 cells
+            float *wrun = buf + __builtin_amdgcn_readfirstlane(q & ~63);
             const T *src = fz;
-            int left = n_in;
-            // eight planes at a time: the loads issue back to back
-            for (; left >= 8; left -= 8) {
-                const __amdgpu_buffer_rsrc_t rs = plane_run(src, 8u * zbytes);
-                float vals[8];
+            for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
+                const int cnt = min(n_in - ic0, 8);
+                const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
+                float *wd = wrun + (n_below + ic0) * plane;
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    vals[u] = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    d[u * plane] = in_xy ? vals[u] : 0.0f;
-                src += 8 * zstride;
-                d += 8 * plane;
-            }
-            if (left > 0) {
-                const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)left * zbytes);
-                for (int u = 0; u < left; ++u) {
-                    const float val = buf_f32<T>(rs, xy, (unsigned)u * zbytes);
-                    d[u * plane] = in_xy ? val : 0.0f;
+                for (int u = 0; u < 8; ++u) {
+                    if (u < cnt) {   // uniform
+                        auto *l = (__attribute__((address_space(3))) void *)(wd + u * plane);
+                        if constexpr (sizeof(T) == 4)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, xy, (unsigned)u * zbytes, 0, 0);
+                        else
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 2, xy, (unsigned)u * zbytes, 0, 0);
+                    }
                 }
+                src += 8 * zstride;
             }
-            for (int ic = n_below + n_in; ic < HC; ++ic)
+        } else {
+            for (int ic = n_below; ic < n_below + n_in; ++ic)
                 dst[ic * plane] = 0.0f;
+        }
+    }
+}
+
+// 16-bit storage: turn a landed slab's words (a value zero-extended in the low
+// half, or an FP32 zero) into FP32 in place; FP32 slabs are left as they are.
+template <typename T>
+__device__ __forceinline__ void widen_slab(float *buf, int words, int tid)
+{
+    if constexpr (sizeof(T) == 2) {
+        uint32_t *w = reinterpret_cast<uint32_t *>(buf);
+        for (int q = tid; q < words; q += 256) {
+            const uint32_t v = w[q];
+            float x;
+            if constexpr (std::is_same<T, f16_t>::value)
+                x = (float)__builtin_bit_cast(f16_t, (uint16_t)v);
+            else
+                x = __uint_as_float(v << 16);
+            w[q] = __float_as_uint(x);
         }
     }
 }
@@ -288,9 +259,9 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
         const int b_lo = box.x, b_hi = box.y, c_lo = box.z, c_hi = box.w;
         const int HB = b_hi - b_lo + 1, HC = c_hi - c_lo + 1;
         const bool staged = HB > 0 && HC > 0 && FP_WA * HB * HC <= FP_LDS_FLOATS;
-        // FP32 slabs that fit one half of the buffer are double-buffered:
-        // slab n + 1 is loaded into the other half while slab n is sampled
-        const bool small = sizeof(T) == 4 && staged && FP_WA * HB * HC <= FP_HALF;
+        // slabs that fit one half of the buffer are double-buffered: slab
+        // n + 1 is loaded into the other half while slab n is sampled
+        const bool small = staged && FP_WA * HB * HC <= FP_HALF;
         float *buf = small ? slab + (n & 1) * FP_HALF : slab;
         if (in_flight) {
             __builtin_amdgcn_s_waitcnt(0);   // this slab's loads have landed in LDS
@@ -302,6 +273,12 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
             __syncthreads();
         }
         in_flight = false;
+        if constexpr (sizeof(T) == 2) {
+            if (staged) {
+                widen_slab<T>(buf, FP_WA * HB * HC, tid);
+                __syncthreads();
+            }
+        }
         if (n + 1 < n_slabs) {
             if ((n + 1) % FP_BOXES == 0) {
                 fill_boxes(n + 1);
