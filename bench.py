@@ -44,8 +44,8 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524316.4, 1048576.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.31957e+07, "write_kib": 1.23782e+06,
-               "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "f91a0caf53719f57"},
+    "fp_cone": {"fetch_kib": 7.25279e+07, "write_kib": 1.23828e+06,
+               "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "99398aca60b65f1d"},
     "bp_cone": {"fetch_kib": 8.56939e+06, "write_kib": 524288,
                "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "75c200fb520e9dd7"},
     "weight_filter": {"fetch_kib": 564843, "write_kib": 1.10592e+06,
