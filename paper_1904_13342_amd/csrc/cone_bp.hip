@@ -358,16 +358,20 @@ __device__ __forceinline__ void clear_tile(int *tile, int tid)
 __device__ __forceinline__ void flush_tile(int *tile, const Footprint &fp, const Geom3D &g, float *qk, float inv,
                                            int tid)
 {
-    for (int r = tid >> 4; r < fp.th; r += 16) {
-        const int gi = fp.v_lo + r;
-        const bool row_ok = (unsigned)gi < (unsigned)g.nv;
-        for (int c = tid & 15; c < fp.tw; c += 16) {
-            const int gj = fp.u_lo + c;
-            const int t = tile[r * BPT_TS + c];
-            tile[r * BPT_TS + c] = 0;
-            if (t != 0 && row_ok && (unsigned)gj < (unsigned)g.nu)
-                unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, (float)t * inv);
-        }
+    // consecutive lanes take consecutive pixels of the footprint, row after
+    // row, so a wave's atomics fall on as few cache lines as possible
+    const int n_pix = fp.th * fp.tw;
+    const float rtw = 1.0f / (float)fp.tw;
+    for (int n = tid; n < n_pix; n += 256) {
+        int r = (int)(((float)n + 0.5f) * rtw);
+        int c = n - r * fp.tw;
+        r += (c >= fp.tw) - (c < 0);
+        c = n - r * fp.tw;
+        const int gi = fp.v_lo + r, gj = fp.u_lo + c;
+        const int t = tile[r * BPT_TS + c];
+        tile[r * BPT_TS + c] = 0;
+        if (t != 0 && (unsigned)gi < (unsigned)g.nv && (unsigned)gj < (unsigned)g.nu)
+            unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, (float)t * inv);
     }
 }
 
