@@ -100,6 +100,7 @@ constexpr int WAVES = 8;         // at most: one workgroup per CU (LDS-bound), t
 constexpr int TS = 65;          // forward transpose [c][b] and twiddle table [k][b], row stride (float2)
 constexpr int US = 33;          // inverse transpose [b][c], row stride (float2)
 constexpr int BUF = 64 * US;    // float2 per wave (>= 32 * TS)
+constexpr int MID = 2 * 32;     // middle-step twiddles [d][p] (float2)
 
 __device__ constexpr int rev5(int k)
 {
@@ -126,8 +127,9 @@ __device__ __forceinline__ float2 tw32(float2 d, int t)
 }
 
 // In-register 32-point DFT (radix-2 decimation in frequency): natural order
-// in, bit-reversed order out (X[k] = v[rev5(k)]).
-template <int DIR>
+// in, bit-reversed order out (X[k] = v[rev5(k)]).  With ZERO_TOP the inputs
+// v[16..31] are known to be zero and the first stage only twiddles.
+template <int DIR, bool ZERO_TOP = false>
 __device__ __forceinline__ void dft32(float2 (&v)[32])
 {
 #pragma unroll
@@ -136,9 +138,13 @@ __device__ __forceinline__ void dft32(float2 (&v)[32])
         for (int j = 0; j < 32; j += 2 * s) {
 #pragma unroll
             for (int k = 0; k < s; ++k) {
-                const float2 x = v[j + k], y = v[j + k + s];
-                v[j + k] = cadd(x, y);
-                v[j + k + s] = tw32<DIR>(csub(x, y), k * (16 / s));
+                if (ZERO_TOP && s == 16) {
+                    v[j + k + s] = tw32<DIR>(v[j + k], k);
+                } else {
+                    const float2 x = v[j + k], y = v[j + k + s];
+                    v[j + k] = cadd(x, y);
+                    v[j + k + s] = tw32<DIR>(csub(x, y), k * (16 / s));
+                }
             }
         }
     }
@@ -181,29 +187,45 @@ __device__ __forceinline__ void wave_sync()
 
 }  // namespace w2k
 
-template <typename T>
+// ZERO_TOP: the rows are at most 1024 samples long, so the upper half of the
+// zero-padded sequence (and of the output) is never touched.
+template <typename T, bool ZERO_TOP>
 __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) weight_filter_2048_kernel(FilterArgs a, const T *__restrict__ in,
                                                                              float *__restrict__ out, long rows)
 {
     using namespace w2k;
+    constexpr int NA = ZERO_TOP ? 16 : 32;   // input and output rows a that can hold samples
     // twt[k TS + b] = w2048^(k b) for k < 32, b < 64: every twiddle of the
-    // pair is read at an offset fixed at compile time from a per-lane base
-    __shared__ float2 lds[32 * TS + WAVES * BUF];
+    // pair is read at an offset fixed at compile time from a per-lane base;
+    // wmid[2 d + p] = w64^d for p = 0 and its conjugate for p = 1
+    __shared__ float2 lds[32 * TS + MID + WAVES * BUF];
     float2 *twt = lds;
-    float2 *buf = lds + 32 * TS + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
+    float2 *wmid = lds + 32 * TS;
+    float2 *buf = lds + 32 * TS + MID + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * BUF;
     for (int n = threadIdx.x; n < 32 * 64; n += blockDim.x)
         twt[(n >> 6) * TS + (n & 63)] = a.tw[(n >> 6) * (n & 63)];   // k b < 2048
+    for (int n = threadIdx.x; n < MID; n += blockDim.x) {
+        const float2 w = a.tw[32 * (n >> 1)];
+        wmid[n] = make_float2(w.x, (n & 1) ? -w.y : w.y);
+    }
     __syncthreads();
     const long pairs = (rows + 1) / 2;
-    // the symmetrised response at this lane's middle-step outputs
-    // k = c + 32 d + 1024 p, d = 0..31 (fixed across pairs, kept in registers)
-    float kr[32];
+    // The output scale: 1/2048 for the inverse transform, times SDD for the
+    // flat detector's cosine weight (applied to the rows below without it).
+    const float oscale = (a.cos_sdd > 0.0f && !a.curved) ? a.cos_sdd / 2048.0f : 1.0f / 2048.0f;
+    // The symmetrised response at the two outputs k0 = c + 32 d and
+    // k1 = k0 + 1024 that meet in this lane's middle step, as their sum and
+    // difference, with the output scale (fixed across pairs, kept in registers).
+    float ks[32], kd[32];
     {
-        const int lc = (threadIdx.x & 63) >> 1, lp = threadIdx.x & 1;
+        const int lc = (threadIdx.x & 63) >> 1;
 #pragma unroll
         for (int d = 0; d < 32; ++d) {
-            const int k = lc + 32 * d + 1024 * lp;
-            kr[d] = 0.5f * (a.K[k] + a.K[(2048 - k) & 2047]);
+            const int k0 = lc + 32 * d, k1 = k0 + 1024;
+            const float K0 = 0.5f * (a.K[k0] + a.K[(2048 - k0) & 2047]);
+            const float K1 = 0.5f * (a.K[k1] + a.K[2048 - k1]);
+            ks[d] = (K0 + K1) * oscale;
+            kd[d] = (K0 - K1) * oscale;
         }
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
@@ -223,7 +245,7 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         const __amdgpu_buffer_rsrc_t sb = row_rsrc(in + (size_t)rb * a.nu * has_b, has_b ? row_bytes : 0u);
         float2 v[32];
 #pragma unroll
-        for (int i = 0; i < 32; ++i)
+        for (int i = 0; i < NA; ++i)
             v[i] = make_float2(row_load<T>(sa, 64 * i + lane), row_load<T>(sb, 64 * i + lane));
         // the weights, one wave-uniform pass per factor present
         const int ia = (int)(ra % a.nv), ka = (int)((ra / a.nv) % a.n_proj);
@@ -232,12 +254,11 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         // cos(u_j / SDD), the same for both rows (the hardware cosine takes
         // revolutions); on a flat detector SDD / sqrt(SDD^2 + u_j^2 + v_i^2),
         // whose factor SDD is applied with the output scale.
-        float oscale = 1.0f / 2048.0f;
         if (a.cos_sdd > 0.0f && a.curved) {
             const float rev = 1.0f / (a.cos_sdd * 6.283185307f);
             const float g0 = ((float)lane - a.cu) * a.du * rev, gs = 64.0f * a.du * rev;
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 const float w = __builtin_amdgcn_cosf(fmaf((float)i, gs, g0));
                 v[i].x *= w;
                 v[i].y *= w;
@@ -247,9 +268,8 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
             const float s2 = a.cos_sdd * a.cos_sdd;
             const float ca = fmaf(va, va, s2), cb = fmaf(vb, vb, s2);
             const float u0 = ((float)lane - a.cu) * a.du, us = 64.0f * a.du;
-            oscale *= a.cos_sdd;
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 const float u = fmaf((float)i, us, u0), uu = u * u;
                 v[i].x *= __builtin_amdgcn_rsqf(uu + ca);
                 v[i].y *= __builtin_amdgcn_rsqf(uu + cb);
@@ -259,7 +279,7 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
             const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W_red + (size_t)ka * a.nu, 4u * a.nu);
             const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W_red + (size_t)kb * a.nu, 4u * a.nu);
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 v[i].x *= row_load<float>(wa, 64 * i + lane);
                 v[i].y *= row_load<float>(wb, 64 * i + lane);
             }
@@ -268,12 +288,12 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
             const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W + (size_t)ia * a.nu, 4u * a.nu);
             const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W + (size_t)ib * a.nu, 4u * a.nu);
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 v[i].x *= row_load<float>(wa, 64 * i + lane);
                 v[i].y *= row_load<float>(wb, 64 * i + lane);
             }
         }
-        dft32<-1>(v);
+        dft32<-1, ZERO_TOP>(v);
 #pragma unroll
         for (int k = 0; k < 32; ++k)
             buf[k * TS + lane] = k == 0 ? v[rev5(0)] : cmul(v[rev5(k)], twt[k * TS + lane]);
@@ -282,23 +302,20 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         for (int m = 0; m < 32; ++m)
             v[m] = buf[c * TS + 2 * m + p];
         dft32<-1>(v);
-        // Per output d (held bit-reversed at v[rev5(d)]): X[c + 32 (d + 32 p)] =
-        // E[d] +- w64^d O[d], times the symmetrised response; then the inverse's
-        // first step, (X0 + (-1)^q X1) w64^(-q d) with q = p, stored in natural
-        // order at v[d].  Bit reversal pairs d with rev5(d), so both entries of a
-        // pair are read before either is written.
-        // twt[d TS + 32 p] is w64^d for p = 1 and 1 for p = 0, and s = (-1)^p, so
-        // every lane runs the same instructions.
-        const float sg = 1.0f - 2.0f * (float)p;
+        // Per output d (held bit-reversed at v[rev5(d)]) lane p = 0 holds the
+        // even half's E[d] and lane p = 1 the odd half's O[d].  The last forward
+        // step gives X0 = E + w O and X1 = E - w O (w = w64^d, at outputs
+        // c + 32 d and c + 32 d + 1024), the response scales them by K0 and K1,
+        // and the inverse's first step forms X0 K0 + X1 K1 and
+        // (X0 K0 - X1 K1) conj(w).  Written out, lane p = 0 needs
+        // (K0 + K1) E + (K0 - K1) w O and lane p = 1 (K0 + K1) O +
+        // (K0 - K1) conj(w) E: its own value, the partner's value times its
+        // wmid entry, and the two response sums.  The result is stored in
+        // natural order at v[d]; bit reversal pairs d with rev5(d), so both
+        // entries of a pair are read before either is written.
         auto mid = [&](int d, float2 g) {
-            const float2 w = twt[d * TS + 32 * p];
-            const float2 mine = cmul(g, w);
-            const float2 other = xor1(mine);
-            const float2 x = make_float2(fmaf(sg, mine.x, other.x), fmaf(sg, mine.y, other.y));
-            const float2 f = make_float2(x.x * kr[d], x.y * kr[d]);
-            const float2 of = xor1(f);
-            const float2 sq = make_float2(fmaf(sg, f.x, of.x), fmaf(sg, f.y, of.y));
-            return cmul(sq, make_float2(w.x, -w.y));
+            const float2 t = cmul(xor1(g), wmid[2 * d + p]);
+            return make_float2(fmaf(ks[d], g.x, kd[d] * t.x), fmaf(ks[d], g.y, kd[d] * t.y));
         };
 #pragma unroll
         for (int d = 0; d < 32; ++d) {
@@ -329,10 +346,10 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         const __amdgpu_buffer_rsrc_t oa = row_rsrc(out + (size_t)ra * a.nu, 4u * a.nu);
         const __amdgpu_buffer_rsrc_t ob = row_rsrc(out + (size_t)rb * a.nu * has_b, has_b ? 4u * a.nu : 0u);
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
+        for (int i = 0; i < NA; ++i) {
             const float2 y = v[rev5(i)];
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x * oscale), oa, (64 * i + lane) * 4, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y * oscale), ob, (64 * i + lane) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.x), oa, (64 * i + lane) * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y.y), ob, (64 * i + lane) * 4, 0, 0);
         }
         wave_sync();   // the inverse transpose has been read before the next pair writes
     }
@@ -529,8 +546,12 @@ hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t 
     const int waves = (int)(per_cu < w2k::WAVES ? per_cu : w2k::WAVES);
     const long groups = (pairs + waves - 1) / waves;
     const unsigned grid = (unsigned)(groups < 256 ? groups : 256);
-    hipLaunchKernelGGL((weight_filter_2048_kernel<T>), dim3(grid), dim3(waves * 64), 0, s, a, (const T *)in, out,
-                       rows);
+    if (a.nu <= 1024)
+        hipLaunchKernelGGL((weight_filter_2048_kernel<T, true>), dim3(grid), dim3(waves * 64), 0, s, a, (const T *)in,
+                           out, rows);
+    else
+        hipLaunchKernelGGL((weight_filter_2048_kernel<T, false>), dim3(grid), dim3(waves * 64), 0, s, a, (const T *)in,
+                           out, rows);
     return hipGetLastError();
 }
 
