@@ -97,9 +97,13 @@ __global__ void __launch_bounds__(WF_THREADS) weight_filter_kernel(FilterArgs a,
 namespace w2k {
 
 constexpr int WAVES = 8;         // at most: one workgroup per CU (LDS-bound), two waves per SIMD
-constexpr int TS = 65;          // forward transpose [c][b] and twiddle table [k][b], row stride (float2)
-constexpr int US = 33;          // inverse transpose [b][c], row stride (float2)
-constexpr int BUF = 64 * US;    // float2 per wave (>= 32 * TS)
+// Row strides (float2) chosen against LDS bank conflicts: lanes (c, p) read
+// [c][2 m + p] of the forward transpose and [c][2 be + p] of the twiddle
+// table, which an even stride of 2 mod 32 spreads over all banks.
+constexpr int TS = 66;          // forward transpose [c][b] and twiddle table [k][b]
+constexpr int US = 33;          // inverse transpose [b][c]
+constexpr int BUF = 64 * US;    // float2 per wave
+static_assert(BUF >= 32 * TS, "the forward transpose fits in the wave's buffer");
 constexpr int MID = 2 * 32;     // middle-step twiddles [d][p] (float2)
 
 __device__ constexpr int rev5(int k)
@@ -187,8 +191,37 @@ __device__ __forceinline__ void wave_sync()
 
 }  // namespace w2k
 
+// The two rows of pair pr: their index ra = 2 pr (rows < 2^30, so 32 bits
+// hold it and the next pair's), whether row b exists, and each row's detector
+// row i and view k in the (batch, view, row) order.
+struct PairRows {
+    unsigned ra;
+    bool has, has_b;
+    int ia, ka, ib, kb;
+};
+
+__device__ __forceinline__ PairRows pair_rows(long pr, long rows, int nv, int n_proj)
+{
+    PairRows r;
+    r.ra = (unsigned)(2 * pr);
+    r.has = (long)r.ra < rows;
+    r.has_b = (long)r.ra + 1 < rows;
+    const unsigned q = r.ra / (unsigned)nv;
+    r.ia = (int)(r.ra - q * (unsigned)nv);
+    r.ka = (int)(q % (unsigned)n_proj);
+    r.ib = r.ia + 1;
+    r.kb = r.ka;
+    if (r.ib == nv) {
+        r.ib = 0;
+        r.kb = r.ka + 1 == n_proj ? 0 : r.ka + 1;
+    }
+    return r;
+}
+
 // ZERO_TOP: the rows are at most 1024 samples long, so the upper half of the
-// zero-padded sequence (and of the output) is never touched.
+// zero-padded sequence (and of the output) is never touched, and the registers
+// this frees hold the next pair's samples and redundancy weights, loaded while
+// the current pair is transformed.
 template <typename T, bool ZERO_TOP>
 __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) weight_filter_2048_kernel(FilterArgs a, const T *__restrict__ in,
                                                                              float *__restrict__ out, long rows)
@@ -230,26 +263,49 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: row bases stay scalar
     const int nw = blockDim.x >> 6;   // waves in this workgroup (1 .. WAVES)
-    for (long pr = (long)blockIdx.x * nw + wave; pr < pairs; pr += (long)gridDim.x * nw) {
-        const long ra = 2 * pr, rb = ra + 1;
-        const bool has_b = rb < rows;
+    const long stride = (long)gridDim.x * nw;
+    const unsigned row_bytes = (unsigned)a.nu * (unsigned)sizeof(T);
+    // the samples of a pair's rows packed as one complex sequence, lane b
+    // holding x[64 a + b], and (ZERO_TOP) their redundancy weights: all loads
+    // in flight at once, zero past nu and for absent rows
+    auto fetch = [&](const PairRows &q, int lane, float2 (&x)[32], float2 (&wr)[32]) {
+        const __amdgpu_buffer_rsrc_t sa = row_rsrc(in + (size_t)q.ra * a.nu, q.has ? row_bytes : 0u);
+        const __amdgpu_buffer_rsrc_t sb = row_rsrc(in + ((size_t)q.ra + 1) * a.nu * q.has_b, q.has_b ? row_bytes : 0u);
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            x[i] = make_float2(row_load<T>(sa, 64 * i + lane), row_load<T>(sb, 64 * i + lane));
+        if (ZERO_TOP && a.W_red) {
+            const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W_red + (size_t)q.ka * a.nu, q.has ? 4u * a.nu : 0u);
+            const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W_red + (size_t)q.kb * a.nu, q.has_b ? 4u * a.nu : 0u);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+                wr[i] = make_float2(row_load<float>(wa, 64 * i + lane), row_load<float>(wb, 64 * i + lane));
+        }
+    };
+    long pr = (long)blockIdx.x * nw + wave;
+    PairRows nxt = pair_rows(pr, rows, a.nv, a.n_proj);
+    float2 px[32], pw[32];   // the prefetched pair (ZERO_TOP)
+    if constexpr (ZERO_TOP)
+        fetch(nxt, threadIdx.x & 63, px, pw);
+    for (; pr < pairs; pr += stride) {
+        const PairRows cur = nxt;
         // The lane index is made opaque per pair so that per-column terms
         // are recomputed rather than hoisted out of the loop and spilled.
         int lane = threadIdx.x & 63;
         asm volatile("" : "+v"(lane));
         const int c = lane >> 1, p = lane & 1;          // roles in the middle steps
-        // the pair's rows packed as one complex sequence, lane b holding
-        // x[64 a + b]: all loads in flight at once, zero past nu
-        const unsigned row_bytes = (unsigned)a.nu * (unsigned)sizeof(T);
-        const __amdgpu_buffer_rsrc_t sa = row_rsrc(in + (size_t)ra * a.nu, row_bytes);
-        const __amdgpu_buffer_rsrc_t sb = row_rsrc(in + (size_t)rb * a.nu * has_b, has_b ? row_bytes : 0u);
-        float2 v[32];
+        float2 v[32], wr[32];
+        if constexpr (ZERO_TOP) {
 #pragma unroll
-        for (int i = 0; i < NA; ++i)
-            v[i] = make_float2(row_load<T>(sa, 64 * i + lane), row_load<T>(sb, 64 * i + lane));
+            for (int i = 0; i < NA; ++i) {
+                v[i] = px[i];
+                wr[i] = pw[i];
+            }
+        } else {
+            fetch(cur, lane, v, wr);
+        }
         // the weights, one wave-uniform pass per factor present
-        const int ia = (int)(ra % a.nv), ka = (int)((ra / a.nv) % a.n_proj);
-        const int ib = (int)(rb % a.nv), kb = (int)((rb / a.nv) % a.n_proj);
+        const int ia = cur.ia, ib = cur.ib;
         // Cosine weights (Kak & Slaney) with u_j = (j - cu) du: on the arc
         // cos(u_j / SDD), the same for both rows (the hardware cosine takes
         // revolutions); on a flat detector SDD / sqrt(SDD^2 + u_j^2 + v_i^2),
@@ -276,12 +332,17 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
             }
         }
         if (a.W_red) {
-            const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W_red + (size_t)ka * a.nu, 4u * a.nu);
-            const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W_red + (size_t)kb * a.nu, 4u * a.nu);
+            if constexpr (!ZERO_TOP) {
+                const __amdgpu_buffer_rsrc_t wa = row_rsrc(a.W_red + (size_t)cur.ka * a.nu, 4u * a.nu);
+                const __amdgpu_buffer_rsrc_t wb = row_rsrc(a.W_red + (size_t)cur.kb * a.nu, 4u * a.nu);
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+                    wr[i] = make_float2(row_load<float>(wa, 64 * i + lane), row_load<float>(wb, 64 * i + lane));
+            }
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
-                v[i].x *= row_load<float>(wa, 64 * i + lane);
-                v[i].y *= row_load<float>(wb, 64 * i + lane);
+                v[i].x *= wr[i].x;
+                v[i].y *= wr[i].y;
             }
         }
         if (a.W) {
@@ -293,6 +354,9 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
                 v[i].y *= row_load<float>(wb, 64 * i + lane);
             }
         }
+        nxt = pair_rows(pr + stride, rows, a.nv, a.n_proj);
+        if constexpr (ZERO_TOP)
+            fetch(nxt, lane, px, pw);
         dft32<-1, ZERO_TOP>(v);
 #pragma unroll
         for (int k = 0; k < 32; ++k)
@@ -343,8 +407,9 @@ __global__ void __launch_bounds__(w2k::WAVES * 64) __attribute__((amdgpu_waves_p
         dft32<1>(v);
         // n < nu is kept (stores past the row's end, or to an absent row b,
         // are dropped by the buffer range check)
-        const __amdgpu_buffer_rsrc_t oa = row_rsrc(out + (size_t)ra * a.nu, 4u * a.nu);
-        const __amdgpu_buffer_rsrc_t ob = row_rsrc(out + (size_t)rb * a.nu * has_b, has_b ? 4u * a.nu : 0u);
+        const __amdgpu_buffer_rsrc_t oa = row_rsrc(out + (size_t)cur.ra * a.nu, 4u * a.nu);
+        const __amdgpu_buffer_rsrc_t ob = row_rsrc(out + ((size_t)cur.ra + 1) * a.nu * cur.has_b,
+                                                   cur.has_b ? 4u * a.nu : 0u);
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const float2 y = v[rev5(i)];
@@ -539,6 +604,8 @@ template <typename T>
 hipError_t wf_2048(const FilterArgs &a, const void *in, float *out, hipStream_t s)
 {
     const long rows = (long)a.batch * a.n_proj * a.nv;
+    if (rows >= (1L << 30))   // row indices are 32-bit
+        return wf_m<T, 2048>(a, in, out, s);
     const long pairs = (rows + 1) / 2;
     // One workgroup per CU. Few pairs spread over the CUs one wave each
     // rather than sharing a few CUs' SIMDs; many fill eight waves per CU.
