@@ -195,8 +195,11 @@ __global__ void __launch_bounds__(256) fpT_cone_kernel(Geom3D g, const ConeFPVie
         const ConeBPView bv = bviews[k];
         const float rw = rcp_nr(dot4(bv.r[2], bcx, bcy, bcz));
         const float cu = dot4(bv.r[0], bcx, bcy, bcz) * rw, cv = dot4(bv.r[1], bcx, bcy, bcz) * rw;
-        const int j_lo = max((int)floorf(min8(cu) + g.cu) - 1, 0), j_hi = min((int)floorf(max8(cu) + g.cu) + 2, g.nu - 1);
-        const int i_lo = max((int)floorf(min8(cv) + g.cv) - 1, 0), i_hi = min((int)floorf(max8(cv) + g.cv) + 2, g.nv - 1);
+        // the corners' floors reduced as integers (floor is monotonic); the
+        // sums are rounded on their own, not fused with the products above
+        const int ju = (int)floorf(__fadd_rn(cu, g.cu)), iv = (int)floorf(__fadd_rn(cv, g.cv));
+        const int j_lo = max(imin8(ju) - 1, 0), j_hi = min(imax8(ju) + 2, g.nu - 1);
+        const int i_lo = max(imin8(iv) - 1, 0), i_hi = min(imax8(iv) + 2, g.nv - 1);
         const int W = j_hi - j_lo + 1, H = i_hi - i_lo + 1;
         if (W <= 0 || H <= 0)
             continue;

@@ -28,6 +28,12 @@ constexpr int BP_TH = 102;   // max staged footprint height (detector rows)
 // each with the largest height that keeps five workgroups per CU.
 constexpr int BP_TS = 78;
 
+// One detector row as a raw buffer: its first word and its length in bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t det_row(const float *row, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(row), (short)0, (int)bytes, 0x00020000);
+}
+
 template <typename TI>
 __device__ __forceinline__ float det_pix(const TI *q, int nu, int nv, int i, int j)
 {
@@ -68,12 +74,14 @@ __device__ __forceinline__ Footprint brick_footprint(const ConeBPView &v, const 
 #pragma clang fp contract(off)
     const float crw = rcp_nr(dot4(v.r[2], cx, cy, cz));
     const float cu = dot4(v.r[0], cx, cy, cz) * crw, cv = dot4(v.r[1], cx, cy, cz) * crw;
-    const float umin = min8(cu), umax = max8(cu), vmin = min8(cv), vmax = max8(cv);
+    // floor is monotonic, so the floor of the extreme corner is the extreme
+    // of the corners' floors
+    const int ju = (int)floorf(cu + g.cu), iv = (int)floorf(cv + g.cv);
     Footprint f;
-    f.u_lo = (int)floorf(umin + g.cu) - 1;
-    f.v_lo = (int)floorf(vmin + g.cv) - 1;
-    f.tw = (int)floorf(umax + g.cu) + 2 - f.u_lo + 1;
-    f.th = (int)floorf(vmax + g.cv) + 2 - f.v_lo + 1;
+    f.u_lo = imin8(ju) - 1;
+    f.v_lo = imin8(iv) - 1;
+    f.tw = imax8(ju) + 2 - f.u_lo + 1;
+    f.th = imax8(iv) + 2 - f.v_lo + 1;
     return f;
 }
 
@@ -196,13 +204,33 @@ __global__ void __launch_bounds__(256) bp_cone_kernel(Geom3D g, const ConeBPView
         const TI *qk = pb + (size_t)k * g.nv * g.nu;
         if (staged) {
             __syncthreads();
-            for (int r = ty; r < th; r += 16) {
-                const int gi = v_lo + r;
-                const bool row_ok = (unsigned)gi < (unsigned)g.nv;
-                const TI *rowp = qk + (size_t)(row_ok ? gi : 0) * g.nu;
-                for (int c = tx; c < tw; c += 16) {
-                    const int gj = u_lo + c;
-                    tile[r * BP_TS + c] = (row_ok && (unsigned)gj < (unsigned)g.nu) ? load_f32(rowp + gj) : 0.0f;
+            // FP32 projections whose footprint lies on the detector: each wave
+            // loads whole tile rows of BP_TW pixels straight into LDS, one
+            // load per row (the pixels past tw are never read; any past the
+            // detector's row end fall outside the row's buffer).  Otherwise
+            // thread by thread, with zeros off the detector.
+            const bool inside = u_lo >= 0 && u_lo + tw <= g.nu && v_lo >= 0 && v_lo + th <= g.nv;
+            if (sizeof(TI) == 4 && inside) {
+                const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+                const int vs = __builtin_amdgcn_readfirstlane(v_lo), hs = __builtin_amdgcn_readfirstlane(th);
+                const unsigned voff = (unsigned)(u_lo + (tid & 63)) * 4u;
+                const unsigned row_bytes = (unsigned)g.nu * 4u;
+                for (int r = wave; r < hs; r += 4) {
+                    const __amdgpu_buffer_rsrc_t rs = det_row((const float *)qk + (size_t)(vs + r) * g.nu, row_bytes);
+                    auto *l = (__attribute__((address_space(3))) void *)(tile + r * BP_TS);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, voff, 0, 0, 0);
+                }
+                __builtin_amdgcn_s_waitcnt(0);   // this wave's rows have landed
+            } else {
+                for (int r = ty; r < th; r += 16) {
+                    const int gi = v_lo + r;
+                    const bool row_ok = (unsigned)gi < (unsigned)g.nv;
+                    const TI *rowp = qk + (size_t)(row_ok ? gi : 0) * g.nu;
+                    for (int c = tx; c < tw; c += 16) {
+                        const int gj = u_lo + c;
+                        tile[r * BP_TS + c] =
+                            (row_ok && (unsigned)gj < (unsigned)g.nu) ? load_f32(rowp + gj) : 0.0f;
+                    }
                 }
             }
             __syncthreads();

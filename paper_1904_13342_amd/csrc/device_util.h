@@ -198,4 +198,23 @@ __device__ __forceinline__ float max8(float x)
     return fmaxf(x, dpp<0x124>(x));
 }
 
+// the same over integers (no NaN handling, so each step is one DPP min/max)
+template <int CTRL>
+__device__ __forceinline__ int dppi(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int imin8(int x)
+{
+    x = min(x, dppi<0xB1>(x));
+    x = min(x, dppi<0x4E>(x));
+    return min(x, dppi<0x124>(x));
+}
+__device__ __forceinline__ int imax8(int x)
+{
+    x = max(x, dppi<0xB1>(x));
+    x = max(x, dppi<0x4E>(x));
+    return max(x, dppi<0x124>(x));
+}
+
 }  // namespace ph
