@@ -38,22 +38,22 @@ OPS_PER_UPDATE = 11.0      # back-projection: v coordinate, floor/fract, 3 lerps
 OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7 lerps, accumulate
 
 # HBM bytes per launch at 512^3 from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
-# what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524316 KiB, WRITE_SIZE 1048576 KiB).
+# what the same counter reads for a plain 1 GiB device-to-device copy (FETCH_SIZE 524315 KiB, WRITE_SIZE 1048576 KiB).
 # A record holds for the kernel's device sources it was taken on (hash below); after any change to them the traffic
 # is reported as null.
 COPY_BYTES = 1 << 30
-COPY_FETCH_KIB, COPY_WRITE_KIB = 524316.4, 1048576.0
+COPY_FETCH_KIB, COPY_WRITE_KIB = 524315.0, 1048576.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.25279e+07, "write_kib": 1.23828e+06,
-               "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "99398aca60b65f1d"},
-    "bp_cone": {"fetch_kib": 8.56939e+06, "write_kib": 524288,
-               "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "75c200fb520e9dd7"},
-    "weight_filter": {"fetch_kib": 564843, "write_kib": 1.10592e+06,
-                     "sources": ('filter.hip', 'fft.h'), "sha256_16": "8b2cc952ec176687"},
-    "fpT_cone": {"fetch_kib": 8.47978e+06, "write_kib": 524288,
-                "sources": ('adjoint.hip', 'device_util.h'), "sha256_16": "45d833951596e357"},
-    "bpT_cone": {"fetch_kib": 2.8169e+06, "write_kib": 2.82697e+07,
-                "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "75c200fb520e9dd7"},
+    "fp_cone": {"fetch_kib": 7.30661e+07, "write_kib": 1.23827e+06,
+             "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "8f67d037ff1f4299"},
+    "bp_cone": {"fetch_kib": 8.28672e+06, "write_kib": 524288,
+             "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e930009cc4c13909"},
+    "weight_filter": {"fetch_kib": 563800, "write_kib": 1.10592e+06,
+                   "sources": ('filter.hip', 'fft.h'), "sha256_16": "89a6c98d7d5f61cc"},
+    "fpT_cone": {"fetch_kib": 8.37076e+06, "write_kib": 524288,
+              "sources": ('adjoint.hip', 'device_util.h'), "sha256_16": "d6d2b86b350f2a7c"},
+    "bpT_cone": {"fetch_kib": 2.80184e+06, "write_kib": 2.45032e+07,
+              "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e930009cc4c13909"},
 }
 
 
