@@ -13,7 +13,9 @@ ones their row grouping and range-checked loads and stores must get right:
 * both weight tables present;
 * a batch of two;
 * half-precision storage;
-* the equiangular (arc) detector with a learned response."""
+* the equiangular (arc) detector with a learned response.
+At M = 2048, rows of at most 1024 bins take the kernel variant that skips the
+zero-padded half and prefetches the next pair; longer rows take the full one."""
 import numpy as np
 import pytest
 import torch
@@ -94,11 +96,12 @@ def test_filter_wave_half_storage(ph, ora, dtype, M):
     check(out, ref, "")
 
 
-@pytest.mark.parametrize("M", [1024, 2048])
-def test_filter_wave_arc_detector_learned(ph, ora, M):
+@pytest.mark.parametrize("M,nu", [(1024, 1000), (2048, 1500), (2048, 1000)])
+def test_filter_wave_arc_detector_learned(ph, ora, M, nu):
     """Equiangular detector (cosine weight cos(gamma)) with a learned
-    response and redundancy weights, 7 views."""
-    nu = 1000 if M == 1024 else 1500
+    response and redundancy weights, 7 views; at M = 2048 both with rows
+    longer than half the transform and with rows of at most 1024 bins (whose
+    zero-padded upper half the kernel skips)."""
     spec = synth.config("fan2d_512").with_(kind="fan2d_curved", det_shape=(nu,), n_proj=7)
     say(f"[filter wave] arc detector, learned K (M = {M}), 7 x {nu}")
     g = ph.from_spec(spec)
