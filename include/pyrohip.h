@@ -118,7 +118,12 @@ int ph_projection_matrices_3d(const ph_geom3d *g, float *mats);
  *   img  : device [batch][ny][nx]        (dtype)      input
  *   sino : device [batch][n_proj][nu]    (dtype)      output
  *   vol  : device [batch][nz][ny][nx]    (dtype)      input
- *   proj : device [batch][n_proj][nv][nu](dtype)      output */
+ *   proj : device [batch][n_proj][nv][nu](dtype)      output
+ * ph_project_cone3d with FP16/BF16 storage widens the volume into an FP32 copy
+ * (4 bytes per voxel, taken and freed in stream order on `stream` with
+ * hipMallocAsync / hipFreeAsync) and projects that: results equal FP32
+ * arithmetic on the stored values, rounded to dtype on store.  If the copy
+ * cannot be allocated the call returns PH_ERR_HIP and writes nothing. */
 int ph_project_par2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,
                      ph_dtype dtype, void *stream);
 int ph_project_fan2d(const ph_geom2d *g, const float *ray_vecs, const void *img, void *sino, int batch,

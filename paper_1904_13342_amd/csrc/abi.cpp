@@ -959,8 +959,22 @@ int ph_project_cone3d(const ph_geom3d *g, const float *mats, const void *vol, vo
     st = prep3d(g, mats, false, &G, &views, &axial);
     if (st != PH_OK)
         return st;
-    return to_status(
-        launch_project_cone(dtype, G, (const ConeFPView *)views, vol, proj, batch, (hipStream_t)stream));
+    const hipStream_t s = (hipStream_t)stream;
+    if (dtype == PH_F32)
+        return to_status(launch_project_cone(dtype, G, (const ConeFPView *)views, (const float *)vol, proj, batch, s));
+    // A half-precision volume is widened (exactly) into a stream-ordered FP32
+    // copy, projected by the FP32 kernel, and the projections are stored in
+    // half precision: the values and arithmetic of FP32 staging, without a
+    // 16-bit staging path.  The copy is freed in stream order.
+    const size_t n_vox = (size_t)batch * G.nx * G.ny * G.nz;
+    void *wide = nullptr;
+    if (hipMallocAsync(&wide, n_vox * sizeof(float), s) != hipSuccess)
+        return PH_ERR_HIP;
+    hipError_t e = launch_cast_to_f32(dtype, vol, (float *)wide, n_vox, s);
+    if (e == hipSuccess)
+        e = launch_project_cone(dtype, G, (const ConeFPView *)views, (const float *)wide, proj, batch, s);
+    const hipError_t ef = hipFreeAsync(wide, s);
+    return to_status(e != hipSuccess ? e : ef);
 }
 
 int ph_backproject_cone3d(const ph_geom3d *g, const float *mats, const void *proj, void *vol, int batch, ph_dtype dtype,

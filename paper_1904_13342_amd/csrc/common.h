@@ -99,7 +99,8 @@ hipError_t launch_project_2d(int dtype, bool fan, const Geom2D &g, const float2 
                              int batch, hipStream_t stream);
 hipError_t launch_backproject_2d(int dtype, bool fan, const Geom2D &g, const float2 *views, const void *sino,
                                  bool sino_is_f32, void *img, int batch, hipStream_t stream);
-hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const void *vol, void *proj,
+// FP32 volume in; projections stored as dtype (FP32, FP16 or BF16)
+hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const float *vol, void *proj,
                                int batch, hipStream_t stream);
 // nz_seg: voxels per thread column segment (16 or 32), chosen by the host
 // so that a brick's detector footprint fits the LDS tile (64 x 128 pixels).
@@ -129,6 +130,8 @@ hipError_t launch_backproject_adjoint_cone(int in_dtype, const Geom3D &g, const 
                                            float *proj, int batch, hipStream_t stream);
 // out[i] = in[i] rounded to the storage type (nearest even)
 hipError_t launch_cast_from_f32(int dtype, const float *in, void *out, size_t n, hipStream_t stream);
+// widens n values of storage type dtype to FP32 (exactly)
+hipError_t launch_cast_to_f32(int dtype, const void *in, float *out, size_t n, hipStream_t stream);
 // zero-fill kernel (used in place of a memset, which would not replay
 // correctly inside a captured graph)
 hipError_t fill_zero(float *p, size_t n, hipStream_t stream);

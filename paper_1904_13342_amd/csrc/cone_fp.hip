@@ -14,8 +14,6 @@
 // with all eight trilinear corners read from LDS.  A sample belongs to
 // exactly one slab, decided by the same FP32 coordinate the interpolation
 // uses.  Slabs that do not fit in LDS read the volume directly.
-#include <type_traits>
-
 #include "device_util.h"
 
 namespace ph {
@@ -111,18 +109,17 @@ __device__ __forceinline__ float sample_lds(const float *slab, float fm, float P
 // the grid are zero; the rest are read through buffer descriptors over runs
 // of eight planes (plane offsets are uniform, the cell's byte offset is per
 // lane) straight into LDS, one word per cell, and are still in flight on
-// return (the caller waits).  A 16-bit load leaves its value zero-extended in
-// the low half of the cell's word; widen_slab then makes the words FP32.
-template <typename T, int AX>
-__device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *buf, int a0, int b_lo, int c_lo, int HB,
-                                           int HC, int tid)
+// return (the caller waits).
+template <int AX>
+__device__ __forceinline__ void stage_slab(const Geom3D &g, const float *f, float *buf, int a0, int b_lo, int c_lo,
+                                           int HB, int HC, int tid)
 {
     const int plane = FP_WA * HB;   // cells per z plane
     const int z_lo = max(c_lo, 0), z_hi = min(c_lo + HC - 1, g.nz - 1);
     const int n_below = min(z_lo - c_lo, HC), n_in = max(z_hi - z_lo + 1, 0);   // n_below + n_in <= HC
     const size_t zstride = (size_t)g.nx * g.ny;
-    const unsigned zbytes = (unsigned)(zstride * sizeof(T));
-    const T *fz = f + (size_t)z_lo * zstride;
+    const unsigned zbytes = (unsigned)(zstride * sizeof(float));
+    const float *fz = f + (size_t)z_lo * zstride;
     // cell q of a plane is LDS word q, so a wave fills 64 consecutive words
     // per plane; columns outside the grid are zeroed
     for (int q = tid; q < plane; q += 256) {
@@ -136,10 +133,10 @@ __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *b
         for (int ic = n_below + n_in; ic < HC; ++ic)
             dst[ic * plane] = 0.0f;
         if (in_xy) {
-            const unsigned xy = (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(T);
+            const unsigned xy = (unsigned)(gy * g.nx + gx) * (unsigned)sizeof(float);
             // first word of this wave's run of 64 cells
             float *wrun = buf + __builtin_amdgcn_readfirstlane(q & ~63);
-            const T *src = fz;
+            const float *src = fz;
             for (int ic0 = 0; ic0 < n_in; ic0 += 8) {
                 const int cnt = min(n_in - ic0, 8);
                 const __amdgpu_buffer_rsrc_t rs = plane_run(src, (unsigned)cnt * zbytes);
@@ -148,10 +145,7 @@ __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *b
                 for (int u = 0; u < 8; ++u) {
                     if (u < cnt) {   // uniform
                         auto *l = (__attribute__((address_space(3))) void *)(wd + u * plane);
-                        if constexpr (sizeof(T) == 4)
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, xy, (unsigned)u * zbytes, 0, 0);
-                        else
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 2, xy, (unsigned)u * zbytes, 0, 0);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, xy, (unsigned)u * zbytes, 0, 0);
                     }
                 }
                 src += 8 * zstride;
@@ -163,29 +157,10 @@ __device__ __forceinline__ void stage_slab(const Geom3D &g, const T *f, float *b
     }
 }
 
-// 16-bit storage: turn a landed slab's words (a value zero-extended in the low
-// half, or an FP32 zero) into FP32 in place; FP32 slabs are left as they are.
-template <typename T>
-__device__ __forceinline__ void widen_slab(float *buf, int words, int tid)
-{
-    if constexpr (sizeof(T) == 2) {
-        uint32_t *w = reinterpret_cast<uint32_t *>(buf);
-        for (int q = tid; q < words; q += 256) {
-            const uint32_t v = w[q];
-            float x;
-            if constexpr (std::is_same<T, f16_t>::value)
-                x = (float)__builtin_bit_cast(f16_t, (uint16_t)v);
-            else
-                x = __uint_as_float(v << 16);
-            w[q] = __float_as_uint(x);
-        }
-    }
-}
-
 // Slab walk of one tile along the dominant axis AX (0: x, 1: y); B is the
 // other horizontal axis, C = z.  LDS layout [c][b][a], a fastest.
-template <typename T, int AX>
-__device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *slab, int *s_range, int4 *s_box,
+template <int AX>
+__device__ __forceinline__ float slab_walk(const Geom3D &g, const float *f, float *slab, int *s_range, int4 *s_box,
                                            const Ray &r, const Ray cr[4], bool hit, int kb, int ke)
 {
     constexpr int BX = 1 - AX;
@@ -268,17 +243,11 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
             __syncthreads();
         } else if (staged) {
             __syncthreads();   // the previous slab has been consumed
-            stage_slab<T, AX>(g, f, buf, a0, b_lo, c_lo, HB, HC, tid);
+            stage_slab<AX>(g, f, buf, a0, b_lo, c_lo, HB, HC, tid);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
         in_flight = false;
-        if constexpr (sizeof(T) == 2) {
-            if (staged) {
-                widen_slab<T>(buf, FP_WA * HB * HC, tid);
-                __syncthreads();
-            }
-        }
         if (n + 1 < n_slabs) {
             if ((n + 1) % FP_BOXES == 0) {
                 fill_boxes(n + 1);
@@ -290,7 +259,7 @@ __device__ __forceinline__ float slab_walk(const Geom3D &g, const T *f, float *s
             // half (slab n - 1) is free
             if (small && nHB > 0 && nHC > 0 && FP_WA * nHB * nHC <= FP_HALF) {
                 const int ns = sgn > 0.0f ? s + 1 : s - 1;
-                stage_slab<T, AX>(g, f, slab + ((n + 1) & 1) * FP_HALF, -2 + ns * FP_D, nb.x, nb.z, nHB, nHC, tid);
+                stage_slab<AX>(g, f, slab + ((n + 1) & 1) * FP_HALF, -2 + ns * FP_D, nb.x, nb.z, nHB, nHC, tid);
                 in_flight = true;
             }
         }
@@ -352,9 +321,11 @@ struct FpWork {
     int ntu, ntiles, ngroups, total;   // total = batch * ngroups * ntiles * FP_VG
 };
 
-template <typename T>
+// The volume is FP32 (a half-precision volume is widened first, exactly);
+// TO is the projections' storage type.
+template <typename TO>
 __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView *__restrict__ views,
-                                                      const T *__restrict__ vol, T *__restrict__ proj, FpWork wk)
+                                                      const float *__restrict__ vol, TO *__restrict__ proj, FpWork wk)
 {
     __shared__ float slab[FP_LDS_FLOATS];
     __shared__ int4 s_box[2 * FP_BOXES];
@@ -373,7 +344,7 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
     const int j = j0 + (tid % FP_TILE), i = i0 + (tid / FP_TILE);
     const bool valid = j < g.nu && i < g.nv;
     const ConeFPView &v = views[k];
-    const T *f = vol + (size_t)b * g.nx * g.ny * g.nz;
+    const float *f = vol + (size_t)b * g.nx * g.ny * g.nz;
 
     const Ray r = make_cone_ray(g, v, valid ? j : j0, valid ? i : i0);
     float lo = -3.0e38f, hi = 3.0e38f;
@@ -416,7 +387,7 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
         my = fminf(my, fabsf(cr[c].e[1]));
     }
     const int ax = mx >= my ? 0 : 1;
-    bool slab_ok = g.step <= fminf(g.sx, fminf(g.sy, g.sz)) && (size_t)g.nx * g.ny * sizeof(T) * 8 <= 0xffffffffu;
+    bool slab_ok = g.step <= fminf(g.sx, fminf(g.sy, g.sz)) && (size_t)g.nx * g.ny * sizeof(float) * 8 <= 0xffffffffu;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const float eA = cr[c].e[ax], eB = cr[c].e[1 - ax];
@@ -431,16 +402,16 @@ __global__ void __launch_bounds__(256) fp_cone_kernel(Geom3D g, const ConeFPView
             acc += sample_global(f, g, ray_coord_biased(P0, r.e[0], m) - RAY_BIAS,
                                  ray_coord_biased(P1, r.e[1], m) - RAY_BIAS, ray_coord_biased(P2, r.e[2], m) - RAY_BIAS);
     } else if (ax == 0) {
-        acc = slab_walk<T, 0>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
+        acc = slab_walk<0>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
     } else {
-        acc = slab_walk<T, 1>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
+        acc = slab_walk<1>(g, f, slab, s_range, s_box, r, cr, hit, kb, ke);
     }
     if (valid)
         store_f32(proj + (((size_t)b * g.n_proj + k) * g.nv + i) * g.nu + j, g.step * acc);
 }
 
-template <typename T>
-hipError_t fp_cone(const Geom3D &g, const ConeFPView *views, const void *vol, void *proj, int batch, hipStream_t s)
+template <typename TO>
+hipError_t fp_cone(const Geom3D &g, const ConeFPView *views, const float *vol, void *proj, int batch, hipStream_t s)
 {
     FpWork wk;
     wk.ntu = (g.nu + FP_TILE - 1) / FP_TILE;
@@ -451,13 +422,13 @@ hipError_t fp_cone(const Geom3D &g, const ConeFPView *views, const void *vol, vo
         return hipErrorInvalidConfiguration;
     wk.total = (int)total;
     const unsigned grid = (unsigned)((total + FP_XCDS - 1) / FP_XCDS * FP_XCDS);
-    hipLaunchKernelGGL((fp_cone_kernel<T>), dim3(grid), dim3(256), 0, s, g, views, (const T *)vol, (T *)proj, wk);
+    hipLaunchKernelGGL((fp_cone_kernel<TO>), dim3(grid), dim3(256), 0, s, g, views, vol, (TO *)proj, wk);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const void *vol, void *proj,
+hipError_t launch_project_cone(int dtype, const Geom3D &g, const ConeFPView *views, const float *vol, void *proj,
                                int batch, hipStream_t stream)
 {
     switch (dtype) {
