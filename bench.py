@@ -44,8 +44,8 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524315.0, 1048576.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 7.30661e+07, "write_kib": 1.23827e+06,
-             "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "8f67d037ff1f4299"},
+    "fp_cone": {"fetch_kib": 7.32213e+07, "write_kib": 1.23817e+06,
+             "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "6784486662f5d56c"},
     "bp_cone": {"fetch_kib": 8.28672e+06, "write_kib": 524288,
              "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e930009cc4c13909"},
     "weight_filter": {"fetch_kib": 563800, "write_kib": 1.10592e+06,
