@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpyrohip.so")
 SOURCES = ["abi.cpp", "proj2d.hip", "cone_bp.hip", "cone_fp.hip", "filter.hip", "adjoint.hip",
-           "corrector.hip", "tv.hip", "noalloc.hip"]
+           "corrector.hip", "tv.hip", "noalloc.hip", "widen.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
