@@ -386,20 +386,26 @@ __device__ __forceinline__ void clear_tile(int *tile, int tid)
 __device__ __forceinline__ void flush_tile(int *tile, const Footprint &fp, const Geom3D &g, float *qk, float inv,
                                            int tid)
 {
-    // consecutive lanes take consecutive pixels of the footprint, row after
-    // row, so a wave's atomics fall on as few cache lines as possible
-    const int n_pix = fp.th * fp.tw;
-    const float rtw = 1.0f / (float)fp.tw;
-    for (int n = tid; n < n_pix; n += 256) {
-        int r = (int)(((float)n + 0.5f) * rtw);
-        int c = n - r * fp.tw;
-        r += (c >= fp.tw) - (c < 0);
-        c = n - r * fp.tw;
-        const int gi = fp.v_lo + r, gj = fp.u_lo + c;
-        const int t = tile[r * BPT_TS + c];
-        tile[r * BPT_TS + c] = 0;
-        if (t != 0 && (unsigned)gi < (unsigned)g.nv && (unsigned)gj < (unsigned)g.nu)
-            unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, (float)t * inv);
+    // Whole footprint rows per wave instruction: a row takes 16, 32 or 64
+    // lanes (the least power of two not below tw), lane c of it column c, so
+    // each row's atomics fall on consecutive pixels of one detector row, and
+    // the row and column need no division.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int tw = __builtin_amdgcn_readfirstlane(fp.tw), th = __builtin_amdgcn_readfirstlane(fp.th);
+    const int v_lo = __builtin_amdgcn_readfirstlane(fp.v_lo);
+    const int lc = tw <= 16 ? 4 : (tw <= 32 ? 5 : 6);   // log2 of the lanes per row
+    const int c = lane & ((1 << lc) - 1), rows = 64 >> lc;
+    const int gj = fp.u_lo + c;
+    const bool in_tile = c < tw, col_ok = (unsigned)gj < (unsigned)g.nu;
+    for (int r = wave * rows + (lane >> lc); r < th; r += 4 * rows) {
+        if (in_tile) {
+            int *cell = tile + r * BPT_TS + c;
+            const int t = *cell;
+            *cell = 0;
+            const int gi = v_lo + r;
+            if (t != 0 && col_ok && (unsigned)gi < (unsigned)g.nv)
+                unsafeAtomicAdd(qk + (size_t)gi * g.nu + gj, (float)t * inv);
+        }
     }
 }
 
