@@ -46,14 +46,14 @@ COPY_FETCH_KIB, COPY_WRITE_KIB = 524315.0, 1048576.0
 MEASURED_TRAFFIC = {
     "fp_cone": {"fetch_kib": 7.32213e+07, "write_kib": 1.23817e+06,
              "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "6784486662f5d56c"},
-    "bp_cone": {"fetch_kib": 8.28672e+06, "write_kib": 524288,
-             "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e930009cc4c13909"},
+    "bp_cone": {"fetch_kib": 8.80846e+06, "write_kib": 524288,
+             "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e1f54f92b2136414"},
     "weight_filter": {"fetch_kib": 563800, "write_kib": 1.10592e+06,
                    "sources": ('filter.hip', 'fft.h'), "sha256_16": "89a6c98d7d5f61cc"},
     "fpT_cone": {"fetch_kib": 8.37076e+06, "write_kib": 524288,
               "sources": ('adjoint.hip', 'device_util.h'), "sha256_16": "d6d2b86b350f2a7c"},
-    "bpT_cone": {"fetch_kib": 2.80184e+06, "write_kib": 2.45032e+07,
-              "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e930009cc4c13909"},
+    "bpT_cone": {"fetch_kib": 2.75112e+06, "write_kib": 2.27029e+07,
+              "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e1f54f92b2136414"},
 }
 
 
