@@ -22,7 +22,7 @@ namespace {
 constexpr int FP_TILE = 16;            // detector tile edge (pixels)
 constexpr int FP_D = 6;                // slab depth (planes along A; D + 1 odd keeps LDS rows off shared banks)
 constexpr int FP_WA = FP_D + 1;        // planes held per slab
-constexpr int FP_LDS_FLOATS = 7680;    // 30 KiB slab capacity (with the boxes: five workgroups per CU)
+constexpr int FP_LDS_FLOATS = 6400;    // 25 KiB slab capacity (with the boxes: six workgroups per CU)
 constexpr int FP_HALF = FP_LDS_FLOATS / 2;   // one buffer of the double-buffered pair
 constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
 constexpr int FP_VG = 8;               // views of one tile scheduled together
