@@ -82,13 +82,29 @@ def test_corrector_grad_parity_corrector_detector(ph, ora):
     assert eK < FP32_TOL and eW < FP32_TOL
 
 
-def test_corrector_grad_skips_dW(ph):
+@pytest.mark.parametrize("n_proj,batch,with_W,with_Wred", [(3, 1, False, True), (5, 1, True, False),
+                                                            (3, 3, True, True), (7, 2, True, False),
+                                                            (17, 1, False, False)])
+def test_corrector_grad_parity_1024_ragged(ph, ora, n_proj, batch, with_W, with_Wred):
+    """The 1024-tap filter on the small detector (41 pixels a row, the rest of
+    each 1024-point row is padding), with batch x view row counts of 3, 5, 9,
+    14 and 17 (odd counts leave the last packed pair one row short), with and
+    without W and W_red."""
+    spec = SMALL.with_(n_proj=n_proj)
+    say(f"[corrector_grad] M=1024 views={n_proj} batch={batch} W={with_W} W_red={with_Wred}")
+    eK, eW = _grad_case(ph, ora, spec, 1024, batch, with_W, with_Wred, seed=60 + n_proj + batch)
+    say(f"  dK rel-L2 {eK:.2e}  dW rel-L2 {eW:.2e}")
+    assert eK < FP32_TOL and eW < FP32_TOL
+
+
+@pytest.mark.parametrize("M", [64, 1024])
+def test_corrector_grad_skips_dW(ph, M):
     spec = SMALL
     g = ph.from_spec(spec)
     nv, nu = spec.det_shape
     p = _rng_tensor((spec.n_proj, nv, nu), 50)
     gq = _rng_tensor((spec.n_proj, nv, nu), 51)
-    K = _rng_tensor((64,), 52)
+    K = _rng_tensor((M,), 52)
     dK_only, none = ph.corrector_grad_3d(g, p, gq, K, want_dW=False)
     assert none is None
     dK, _ = ph.corrector_grad_3d(g, p, gq, K)
