@@ -44,8 +44,8 @@ OPS_PER_SAMPLE = 26.0      # forward projection: 3 coordinates, 3 floor/fract, 7
 COPY_BYTES = 1 << 30
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524315.0, 1048576.0
 MEASURED_TRAFFIC = {
-    "fp_cone": {"fetch_kib": 1.06412e+08, "write_kib": 1.23366e+06,
-             "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "071cd13a8e0aad52"},
+    "fp_cone": {"fetch_kib": 6.47788e+07, "write_kib": 1.24095e+06,
+             "sources": ('cone_fp.hip', 'device_util.h'), "sha256_16": "3689f3d998d3b903"},
     "bp_cone": {"fetch_kib": 8.80846e+06, "write_kib": 524288,
              "sources": ('cone_bp.hip', 'device_util.h'), "sha256_16": "e1f54f92b2136414"},
     "weight_filter": {"fetch_kib": 563800, "write_kib": 1.10592e+06,

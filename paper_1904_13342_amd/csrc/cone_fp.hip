@@ -25,7 +25,7 @@ constexpr int FP_WA = FP_D + 1;        // planes held per slab
 constexpr int FP_LDS_FLOATS = 6400;    // 25 KiB slab capacity (with the boxes: six workgroups per CU)
 constexpr int FP_HALF = FP_LDS_FLOATS / 2;   // one buffer of the double-buffered pair
 constexpr int FP_BIAS = (int)RAY_BIAS;  // biased coordinates stay positive (floor == truncation)
-constexpr int FP_VG = 8;               // views of one tile scheduled together
+constexpr int FP_VG = 12;              // views of one tile scheduled together (measured: 4-36)
 constexpr int FP_XCDS = 8;             // accelerator complex dies, each with its own L2
 constexpr int FP_BOXES = 32;           // slab cross-sections computed per batch (ring of two batches)
 
